@@ -1,0 +1,171 @@
+/* lbm3.h -- C ABI of the MI355X (gfx950) library for the three-phase colour-gradient D2Q9
+ * lattice update of Li, Lu, Jiang & Liu, "Lattice Boltzmann simulation of three-phase flows
+ * with moving contact lines on curved surfaces" (arXiv:2102.04709).
+ *
+ * One time step (Sec. II of the paper) is: partial densities and mass fractions C_k (Eq. 16,
+ * C_k = rho_k / rho), the characteristic-line wetting fill of C at solid boundary nodes
+ * (Sec. II B, Eq. 19-22), colour gradients (Eq. 12), the interfacial force (Eq. 10), velocity
+ * (Eq. 11), MRT collision with forcing (Eq. 1-9) at the mixture relaxation time (Eq. 7),
+ * recolouring (Eq. 13-15) and streaming (Eq. 16) with halfway bounce-back, interpolated
+ * bounce-back on exact circles, the fluid-1/fluid-3 exchanging periodic boundary (Sec. III C)
+ * or a Zou-He velocity inlet and pressure outlet (Sec. III D).
+ *
+ * Conventions for every call:
+ *  - Every call returns an lbm3_status; nothing aborts and no exception crosses the ABI.
+ *    lbm3_last_error() gives the message of the last failure on a context.
+ *  - Parameters are validated on the host before any device work.
+ *  - Host inputs are copied during the call.  Device memory passed in (workspace, state and
+ *    field buffers) belongs to the caller and must outlive the context.
+ *  - All device work is enqueued on the stream given at creation; only lbm3_mass,
+ *    lbm3_kernel_times and lbm3_autotune synchronise that stream.
+ *  - A context is not thread-safe; separate contexts on separate streams are independent.
+ *  - Lattice node (i, j) sits at (x, y) = (i, j); host arrays are [ny][nx] with x fastest.
+ *  - Fluids 1, 2, 3 are the paper's red, green and blue.
+ */
+#ifndef LBM3_H
+#define LBM3_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm3_ctx lbm3_ctx; /* opaque; created by lbm3_create, freed by lbm3_destroy */
+
+typedef enum {
+  LBM3_OK = 0,
+  LBM3_EINVAL = 1,      /* invalid argument or inconsistent physical parameters */
+  LBM3_ENOMEM = 2,      /* workspace too small or host allocation failed */
+  LBM3_EHIP = 3,        /* a HIP runtime call failed */
+  LBM3_ESTATE = 4,      /* call not valid in the context's current state */
+  LBM3_ENUMERIC = 5,    /* a NaN or Inf was found in the densities */
+  LBM3_EUNSUPPORTED = 6 /* combination of options not supported */
+} lbm3_status;
+
+/* Arithmetic and storage of the distributions (the densities rho_k are stored in the compute
+ * type).  The distributions are stored as the shift f_a - w_a (rho^0 = 1). */
+typedef enum {
+  LBM3_F64 = 0,          /* FP64 compute and storage */
+  LBM3_F32 = 1,          /* FP32 compute and storage */
+  LBM3_F32_STORE_F16 = 2 /* FP32 compute, FP16 storage of the shifted distributions */
+} lbm3_precision;
+
+/* Boundary in x. */
+typedef enum {
+  LBM3_X_PERIODIC = 0,        /* periodic */
+  LBM3_X_PERIODIC_SWAP13 = 1, /* periodic; populations crossing x exchange fluids 1 and 3
+                                 (Sec. III C modified periodic condition) */
+  LBM3_X_ZOUHE = 2            /* Zou-He velocity inlet (u_in, 0) at x = 0 carrying pure
+                                 fluid 3, pressure outlet rho_out at x = nx-1 carrying the
+                                 node's own composition (Sec. III D); needs y_periodic = 1 and
+                                 no solid within 3 columns of either end */
+} lbm3_bc_x;
+
+/* One domain.  Equal densities rho_k^0 = 1 (Sec. II A), so the dynamic viscosity of each pure
+ * fluid equals its kinematic viscosity nu_k. */
+typedef struct {
+  int32_t nx, ny;        /* lattice nodes, >= 3 each */
+  int32_t y_periodic;    /* 1: periodic in y; 0: every node outside 0 <= y < ny is solid
+                            (flat walls are solid rows inside the mask) */
+  int32_t bc_x;          /* lbm3_bc_x */
+  double u_in, rho_out;  /* Zou-He inlet velocity and outlet density (bc_x = LBM3_X_ZOUHE) */
+  double nu[3];          /* viscosities; tau = 1/2 + 3 nu must lie in (0.5, 10] (Eq. 7) */
+  double sigma[3];       /* sigma12, sigma13, sigma23, each > 0 (Eq. 10, Eq. 15) */
+  double theta_deg[2];   /* theta13, theta23 in (0, 180) degrees, measured inside fluids 1
+                            and 2; theta12 follows from Eq. (18) and must satisfy
+                            |cos theta12| <= 1 */
+  double body_force[2];  /* uniform acceleration added as rho*g to the interfacial force
+                            (test hook; 0 for the paper's cases) */
+  int32_t n_circles;     /* number of exact solid circles (for interpolated bounce-back) */
+  int32_t reserved;      /* must be 0 */
+  const double *circles; /* host [3*n_circles] (cx, cy, R); NULL if n_circles = 0.  A solid
+                            link whose solid node lies in a circle uses Bouzidi interpolated
+                            bounce-back with the exact wall distance; other solid links use
+                            halfway bounce-back.  Not allowed with LBM3_X_PERIODIC_SWAP13. */
+  const uint8_t *solid;  /* host [ny*nx], 1 = solid; copied */
+  const double *rho_init;/* host [3][ny*nx] initial partial densities (velocity 0); copied */
+} lbm3_domain;
+
+typedef struct {
+  int32_t precision;         /* lbm3_precision */
+  int32_t graph_block_steps; /* > 0: lbm3_step replays a captured hipGraph of this many steps
+                                (rounded up to even); 0: plain launches */
+  double beta0;              /* reference segregation parameter of Eq. (14); <= 0 selects the
+                                paper's 0.7 */
+  int32_t tile_x, tile_y;    /* tile of the fused step kernel; 0 selects the default or the
+                                autotuned shape */
+  int32_t persistent_blocks; /* > 0: the fused kernel runs this many work-groups that loop over
+                                the (domain, tile) work list; 0: one work-group per tile */
+  int32_t reserved;          /* must be 0 */
+} lbm3_options;
+
+/* Bytes of device workspace lbm3_create needs for n domains (d[0..n-1]) and these options. */
+lbm3_status lbm3_workspace_bytes(const lbm3_domain *d, int32_t n, const lbm3_options *o,
+                                 size_t *bytes);
+
+/* Validates the domains (Eq. 18, tensions, viscosities, masks -- every fill node must have a
+ * solid normal and its normal line must reach a fluid node), builds the boundary tables
+ * (Eq. 19-20 normals, link fractions), lays out and initialises the state in the caller's
+ * device workspace (256-byte aligned, at least lbm3_workspace_bytes long), and returns a
+ * context.  hip_stream is a hipStream_t (NULL = the null stream).  Synchronises the stream
+ * once at the end.  n = 1 is a single domain; n > 1 advances all domains together. */
+lbm3_status lbm3_create(const lbm3_domain *d, int32_t n, const lbm3_options *o,
+                        void *dev_workspace, size_t bytes, void *hip_stream, lbm3_ctx **out);
+
+/* Advances every domain by nsteps time steps (asynchronous). */
+lbm3_status lbm3_step(lbm3_ctx *c, int32_t nsteps);
+
+/* Runs only the wetting fill (Eq. 21-22) on the current state, writing C into the solid
+ * boundary slots; the next lbm3_step recomputes it.  For stage-by-stage checks. */
+lbm3_status lbm3_fill(lbm3_ctx *c);
+
+/* Writes fields of domain `domain` into caller device buffers of element type dtype
+ * (LBM3_F64 -> double, LBM3_F32 -> float), layout [comp][ny][nx]:
+ *   dev_rho [3]: partial densities at fluid nodes; at solid boundary nodes the C filled by the
+ *                last fill on this state (lbm3_fill), 0 at other solid nodes;
+ *   dev_u   [2]: velocity of Eq. (11) including the interfacial force of the current state
+ *                (0 at solid nodes); may be NULL;
+ *   dev_force [2]: interfacial force of Eq. (10) plus the body force; may be NULL.
+ * Runs the fill first.  Asynchronous. */
+lbm3_status lbm3_fields(lbm3_ctx *c, int32_t domain, void *dev_rho, void *dev_u,
+                        void *dev_force, int32_t dtype);
+
+/* Per-fluid mass sum_x rho_k over fluid nodes, in FP64 and a fixed summation order, for every
+ * domain: host_out[3*n].  Synchronises.  Returns LBM3_ENUMERIC if a NaN/Inf was found. */
+lbm3_status lbm3_mass(lbm3_ctx *c, double *host_out);
+
+/* Checkpointing of the whole state (all domains): a device-to-device copy of the raw state
+ * planes.  set_state(get_state(s)) continues bit-identically. */
+lbm3_status lbm3_state_bytes(const lbm3_ctx *c, size_t *bytes);
+lbm3_status lbm3_get_state(lbm3_ctx *c, void *dev_dst);
+lbm3_status lbm3_set_state(lbm3_ctx *c, const void *dev_src);
+
+/* Average device time (ms) of the wetting-fill and fused-step kernels over nsteps plain steps,
+ * from HIP events recorded on the context's stream around each launch.  Advances the state by
+ * nsteps.  Synchronises. */
+lbm3_status lbm3_kernel_times(lbm3_ctx *c, int32_t nsteps, double *ms_fill, double *ms_step);
+
+/* Times the candidate tile shapes of the fused kernel on the current state (restoring it
+ * afterwards) and keeps the fastest; returns it in tile_xy[2].  Synchronises. */
+lbm3_status lbm3_autotune(lbm3_ctx *c, int32_t steps_per_candidate, int32_t *tile_xy);
+
+/* Information: key 0 = algorithmic bytes per lattice update of the fused kernel (state read
+ * once and written once), 1 = total nodes, 2 = fill nodes, 3 = interpolated-bounce-back nodes,
+ * 4 = tile_x, 5 = tile_y, 6 = work items (tiles), 7 = steps taken. */
+lbm3_status lbm3_query(const lbm3_ctx *c, int32_t key, double *value);
+
+const char *lbm3_last_error(const lbm3_ctx *c);
+/* Message of the last failed lbm3_workspace_bytes or lbm3_create on the calling thread (those
+ * calls have no context to attach it to). */
+const char *lbm3_plan_error(void);
+const char *lbm3_status_string(int32_t code);
+
+/* Frees host bookkeeping, graphs and events; never frees the caller's workspace. */
+void lbm3_destroy(lbm3_ctx *c);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM3_H */

@@ -1,0 +1,829 @@
+// lbm3_api.cpp -- host side of liblbm3: validation, the one-time boundary set-up and the C ABI
+// declared in include/lbm3.h.
+//
+// One-time set-up per domain (Sec. II B of arXiv:2102.04709):
+//   - theta12 from the Young relations, Eq. (17)-(18), and g(X_kl) of Eq. (15);
+//   - node categories: a solid node touching a fluid node in the D2Q9 8-neighbourhood is a
+//     boundary node (C_SB); solid nodes touching C_SB form a second filled layer, because the
+//     stress divergence of Eq. (10) at a boundary fluid node reads the stress of its C_SB
+//     neighbours, whose own gradient reaches one node further into the solid;
+//   - fluid-pointing unit normals by Eq. (19)-(20) (integer weights 960, 448, 84, 32, 1 in units
+//     of 1/5040, summed exactly), and a check that every normal line reaches the fluid;
+//   - link fractions q of the interpolated bounce-back on the exact circles (FP64);
+//   - the (domain, tile) work list of the fused kernel.
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lbm3.h"
+#include "lbm3_internal.h"
+#include "lbm3_kernels.h"
+
+using namespace lbm3;
+
+namespace {
+
+const int kEX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+const int kEY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+const double kPI = 3.14159265358979323846;
+
+struct TileShape {
+  int tx, ty;
+};
+// Candidate tiles of the fused kernel (the autotuner picks among them).
+const TileShape kTiles[] = {{32, 8}, {64, 4}, {64, 8}, {32, 16}, {128, 4}, {16, 16}, {64, 16}, {128, 8}};
+const int kMinTileArea = 256;
+
+int round_up(int v, int m) { return (v + m - 1) / m * m; }
+
+struct DomHost {
+  DomainDev dd;
+  std::vector<uint8_t> flags;   // [(ny+4) * pitch]
+  std::vector<FillNode> fill;
+  std::vector<IbbNode> ibb;
+};
+
+struct Layout {
+  size_t off_F[2], off_R[2], off_flags, off_fill, off_ibb, off_doms, off_work, off_partial,
+      off_chunk_dom, off_chunk_first, off_mass, off_bad, total;
+  int64_t total_plane;
+  int n_fill, n_ibb, n_chunks, max_work;
+};
+
+size_t s_size(int precision) { return precision == LBM3_F64 ? 8 : (precision == LBM3_F32 ? 4 : 2); }
+size_t t_size(int precision) { return precision == LBM3_F64 ? 8 : 4; }
+
+double g_of_X(double X) {
+  if (X < -1.0) return 1.0;
+  if (X < 0.0) return 1.0 - std::sqrt(1.0 - X * X);
+  if (X <= 1.0) return std::sqrt(1.0 - X * X) - 1.0;
+  return -1.0;
+}
+
+bool validate_and_build(const lbm3_domain &d, int dom, double beta0, DomHost &H, std::string &err) {
+  char buf[256];
+  auto fail = [&](const char *m) {
+    snprintf(buf, sizeof buf, "domain %d: %s", dom, m);
+    err = buf;
+    return false;
+  };
+  if (d.nx < 3 || d.ny < 3) return fail("nx and ny must be >= 3");
+  if (d.bc_x < 0 || d.bc_x > 2) return fail("bc_x must be 0, 1 or 2");
+  if (d.reserved != 0) return fail("reserved must be 0");
+  if (d.bc_x == LBM3_X_ZOUHE && !d.y_periodic) return fail("the Zou-He x boundary requires y_periodic = 1");
+  if (d.bc_x == LBM3_X_PERIODIC_SWAP13 && d.n_circles > 0) return fail("circles are not allowed with the fluid-exchanging periodic boundary");
+  if (d.n_circles < 0 || (d.n_circles > 0 && !d.circles)) return fail("bad circle list");
+  if (!d.solid || !d.rho_init) return fail("solid and rho_init are required");
+  if (d.bc_x == LBM3_X_ZOUHE && !(std::fabs(d.u_in) < 0.5 && d.rho_out > 0.0)) return fail("bad Zou-He inlet velocity or outlet density");
+  for (int k = 0; k < 3; ++k) {
+    if (!(d.sigma[k] > 0.0)) return fail("every interfacial tension must be > 0");
+    const double tau = 0.5 + 3.0 * d.nu[k];
+    if (!(tau > 0.5 && tau <= 10.0)) return fail("viscosity gives tau outside (0.5, 10]");
+  }
+  for (int k = 0; k < 2; ++k)
+    if (!(d.theta_deg[k] > 0.0 && d.theta_deg[k] < 180.0)) return fail("contact angles must lie in (0, 180) degrees");
+  const double th13 = d.theta_deg[0] * kPI / 180.0, th23 = d.theta_deg[1] * kPI / 180.0;
+  // Eq. (18) with theta31 = pi - theta13.
+  double c12 = (d.sigma[1] * std::cos(th13) - d.sigma[2] * std::cos(th23)) / d.sigma[0];
+  if (std::fabs(c12) > 1.0 + 1e-12) return fail("contact angles and tensions violate Eq. (18): |cos theta12| > 1");
+  c12 = std::min(1.0, std::max(-1.0, c12));
+  const int nx = d.nx, ny = d.ny;
+  const int pitch = round_up(nx, 64);
+  const int rows = ny + 4;
+  DomainDev &D = H.dd;
+  memset(&D, 0, sizeof D);
+  D.nx = nx;
+  D.ny = ny;
+  D.pitch = pitch;
+  D.yper = d.y_periodic ? 1 : 0;
+  D.bcx = d.bc_x;
+  D.plane = (int64_t)pitch * rows;
+  D.u_in = d.u_in;
+  D.rho_out = d.rho_out;
+  for (int k = 0; k < 3; ++k) {
+    D.nu[k] = d.nu[k];
+    D.sig[k] = d.sigma[k];
+  }
+  {  // X_kl of Eq. (15) for pairs 12, 13, 23 (m is the third fluid)
+    const double s12 = d.sigma[0], s13 = d.sigma[1], s23 = d.sigma[2];
+    D.gX[0] = g_of_X((s13 * s13 + s23 * s23 - s12 * s12) / (2.0 * s13 * s23));
+    D.gX[1] = g_of_X((s12 * s12 + s23 * s23 - s13 * s13) / (2.0 * s12 * s23));
+    D.gX[2] = g_of_X((s12 * s12 + s13 * s13 - s23 * s23) / (2.0 * s12 * s13));
+  }
+  D.beta0 = beta0;
+  D.th13 = th13;
+  D.th23 = th23;
+  D.th12 = std::acos(c12);
+  D.g[0] = d.body_force[0];
+  D.g[1] = d.body_force[1];
+
+  if (d.bc_x == LBM3_X_ZOUHE)
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < 3; ++i)
+        if (d.solid[(size_t)j * nx + i] || d.solid[(size_t)j * nx + nx - 1 - i]) return fail("solid nodes within 3 columns of a Zou-He boundary");
+
+  // Base solid indicator on rows -2..ny+1; padding columns and unused rows are solid.
+  H.flags.assign((size_t)rows * pitch, FL_SOLID);
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) H.flags[plane_index(i, j, pitch)] = d.solid[(size_t)j * nx + i] ? FL_SOLID : 0;
+  const bool yper = D.yper;
+  const bool zh = D.bcx == BCX_ZOUHE;
+  const int jlo = yper ? 0 : -2, jhi = yper ? ny - 1 : ny + 1;
+  // s(x) of Eq. (19): solid beyond a non-periodic y boundary, fluid beyond a Zou-He column.
+  auto solid_at = [&](int i, int j) -> bool {
+    if (zh) {
+      if (i < 0 || i >= nx) return false;
+    } else {
+      i = ((i % nx) + nx) % nx;
+    }
+    if (yper) j = ((j % ny) + ny) % ny;
+    else if (j < -2 || j > ny + 1) return true;
+    return H.flags[plane_index(i, j, pitch)] & FL_SOLID;
+  };
+  auto fluid_at = [&](int i, int j) -> bool {
+    if (zh) {
+      if (i < 0 || i >= nx) return false;
+    } else {
+      i = ((i % nx) + nx) % nx;
+    }
+    if (yper) j = ((j % ny) + ny) % ny;
+    else if (j < 0 || j >= ny) return false;
+    return !(H.flags[plane_index(i, j, pitch)] & FL_SOLID);
+  };
+  // C_SB: solid nodes with a fluid node among their 8 neighbours.
+  std::vector<uint8_t> cat((size_t)rows * pitch, 0);  // 1 = C_SB, 2 = second layer
+  for (int j = jlo; j <= jhi; ++j)
+    for (int i = 0; i < nx; ++i) {
+      if (!solid_at(i, j)) continue;
+      for (int a = 1; a < 9; ++a)
+        if (fluid_at(i + kEX[a], j + kEY[a])) {
+          cat[plane_index(i, j, pitch)] = 1;
+          break;
+        }
+    }
+  auto is_sb = [&](int i, int j) -> bool {
+    if (zh) {
+      if (i < 0 || i >= nx) return false;
+    } else {
+      i = ((i % nx) + nx) % nx;
+    }
+    if (yper) j = ((j % ny) + ny) % ny;
+    else if (j < -2 || j > ny + 1) return false;
+    return cat[plane_index(i, j, pitch)] == 1;
+  };
+  for (int j = jlo; j <= jhi; ++j)
+    for (int i = 0; i < nx; ++i) {
+      const int64_t p = plane_index(i, j, pitch);
+      if (!solid_at(i, j) || cat[p] == 1) continue;
+      for (int a = 1; a < 9; ++a)
+        if (is_sb(i + kEX[a], j + kEY[a])) {
+          cat[p] = 2;
+          break;
+        }
+    }
+  // Fill list with Eq. (19)-(20) normals.
+  for (int pass = 1; pass <= 2; ++pass)
+    for (int j = jlo; j <= jhi; ++j)
+      for (int i = 0; i < nx; ++i) {
+        const int64_t p = plane_index(i, j, pitch);
+        if (cat[p] != pass) continue;
+        long sx = 0, sy = 0;
+        for (int cy = -2; cy <= 2; ++cy)
+          for (int cx = -2; cx <= 2; ++cx) {
+            const int r2 = cx * cx + cy * cy;
+            if (r2 == 0 || !solid_at(i + cx, j + cy)) continue;
+            const long w = r2 == 1 ? 960 : r2 == 2 ? 448 : r2 == 4 ? 84 : r2 == 5 ? 32 : 1;
+            sx += w * cx;
+            sy += w * cy;
+          }
+        if (sx == 0 && sy == 0) {
+          snprintf(buf, sizeof buf, "degenerate solid normal at node (%d,%d)", i, j);
+          return fail(buf);
+        }
+        const double len = std::sqrt((double)sx * sx + (double)sy * sy);
+        FillNode fn;
+        fn.dom = dom;
+        fn.i = i;
+        fn.j = j;
+        fn.li = (int32_t)p;
+        fn.nx = -(double)sx / len;
+        fn.ny = -(double)sy / len;
+        if (!march_line(i, j, fn.nx, fn.ny, fluid_at).ok) {
+          snprintf(buf, sizeof buf, "the normal line from solid node (%d,%d) reaches no fluid node", i, j);
+          return fail(buf);
+        }
+        H.flags[p] |= FL_FILL;
+        H.fill.push_back(fn);
+      }
+  // Interpolated bounce-back link fractions.
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      const int64_t p = plane_index(i, j, pitch);
+      if (H.flags[p] & FL_SOLID) continue;
+      IbbNode node;
+      node.li = (int32_t)p;
+      node.dom = dom;
+      bool any = false;
+      for (int a = 1; a < 9; ++a) {
+        node.q[a - 1] = 0.5;
+        const int si = i - kEX[a], sj = j - kEY[a];
+        if (zh && (si < 0 || si >= nx)) continue;
+        if (fluid_at(si, sj)) continue;
+        bool found = false;
+        double q = 0.5;
+        for (int c = 0; c < d.n_circles; ++c) {
+          for (int ix = -1; ix <= 1; ++ix)
+            for (int iy = -1; iy <= 1; ++iy) {
+              if (ix && zh) continue;
+              if (iy && !yper) continue;
+              const double cx = d.circles[3 * c] + ix * nx, cy = d.circles[3 * c + 1] + iy * ny, R = d.circles[3 * c + 2];
+              const double dxs = si - cx, dys = sj - cy, dxf = i - cx, dyf = j - cy;
+              if (dxs * dxs + dys * dys > R * R) continue;
+              if (dxf * dxf + dyf * dyf <= R * R) continue;
+              const double a2 = kEX[a] * kEX[a] + kEY[a] * kEY[a];
+              const double b = kEX[a] * dxf + kEY[a] * dyf;
+              const double cc = dxf * dxf + dyf * dyf - R * R;
+              const double disc = b * b - a2 * cc;
+              const double qq = (b - std::sqrt(std::max(disc, 0.0))) / a2;
+              if (!found || qq < q) q = qq;
+              found = true;
+            }
+        }
+        if (found) {
+          node.q[a - 1] = std::min(std::max(q, 1e-6), 1.0);
+          any = true;
+        }
+      }
+      if (any) {
+        H.flags[p] |= FL_CURVED;
+        H.ibb.push_back(node);
+      }
+    }
+  return true;
+}
+
+int tiles_of(int nx, int ny, int tx, int ty) { return ((nx + tx - 1) / tx) * ((ny + ty - 1) / ty); }
+
+bool plan(const lbm3_domain *d, int n, const lbm3_options *o, std::vector<DomHost> &H, Layout &L,
+          std::string &err) {
+  if (!d || n < 1) return err = "need at least one domain", false;
+  if (!o) return err = "options are required", false;
+  if (o->precision < 0 || o->precision > 2) return err = "bad precision", false;
+  if (o->reserved != 0) return err = "reserved must be 0", false;
+  if (o->tile_x < 0 || o->tile_y < 0 || o->graph_block_steps < 0 || o->persistent_blocks < 0) return err = "negative option", false;
+  if (o->tile_x > 0 || o->tile_y > 0) {
+    const int area = o->tile_x * o->tile_y;
+    if (o->tile_x <= 0 || o->tile_y <= 0 || area < kMinTileArea || area > 4096 ||
+        step_smem_bytes(o->precision, o->tile_x, o->tile_y) > 160 * 1024)
+      return err = "tile shape out of range (area 256..4096, LDS <= 160 KiB)", false;
+  }
+  const double beta0 = o->beta0 > 0 ? o->beta0 : 0.7;
+  H.assign(n, DomHost());
+  for (int i = 0; i < n; ++i)
+    if (!validate_and_build(d[i], i, beta0, H[i], err)) return false;
+  int64_t base = 0;
+  int nf = 0, ni = 0, nch = 0, maxw = 0;
+  for (int i = 0; i < n; ++i) {
+    H[i].dd.base = base;
+    base += H[i].dd.plane;
+    H[i].dd.fill_off = nf;
+    H[i].dd.n_fill = (int)H[i].fill.size();
+    nf += H[i].dd.n_fill;
+    H[i].dd.ibb_off = ni;
+    H[i].dd.n_ibb = (int)H[i].ibb.size();
+    ni += H[i].dd.n_ibb;
+    nch += (d[i].ny + 15) / 16;
+    int mw = 0;
+    for (const TileShape &t : kTiles) mw = std::max(mw, tiles_of(d[i].nx, d[i].ny, t.tx, t.ty));
+    if (o->tile_x > 0 && o->tile_y > 0) mw = std::max(mw, tiles_of(d[i].nx, d[i].ny, o->tile_x, o->tile_y));
+    maxw += mw;
+  }
+  const int prec = o->precision;
+  L.total_plane = base;
+  L.n_fill = nf;
+  L.n_ibb = ni;
+  L.n_chunks = nch;
+  L.max_work = maxw;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t r = off;
+    off += (bytes + 255) / 256 * 256;
+    return r;
+  };
+  for (int b = 0; b < 2; ++b) {
+    L.off_F[b] = take(9 * (size_t)base * s_size(prec));
+    L.off_R[b] = take(3 * (size_t)base * t_size(prec));
+  }
+  L.off_flags = take((size_t)base);
+  L.off_fill = take(sizeof(FillNode) * std::max(nf, 1));
+  L.off_ibb = take(sizeof(IbbNode) * std::max(ni, 1));
+  L.off_doms = take(sizeof(DomainDev) * n);
+  L.off_work = take(sizeof(WorkItem) * maxw);
+  L.off_partial = take(sizeof(double) * 3 * nch);
+  L.off_chunk_dom = take(sizeof(int) * nch);
+  L.off_chunk_first = take(sizeof(int) * (n + 1));
+  L.off_mass = take(sizeof(double) * 3 * n);
+  L.off_bad = take(sizeof(int));
+  L.total = off;
+  return true;
+}
+
+}  // namespace
+
+struct lbm3_ctx {
+  int n = 0;
+  int precision = 0;
+  hipStream_t stream = nullptr;
+  hipStream_t cap_stream = nullptr;
+  std::vector<DomainDev> doms;
+  Layout L;
+  char *ws = nullptr;
+  int cur = 0;
+  long steps = 0;
+  int tx = 32, ty = 8;
+  int persistent = 0;
+  int graph_block = 0;
+  std::vector<WorkItem> work;
+  hipGraphExec_t graph = nullptr;
+  bool graph_valid = false;
+  std::string err;
+
+  template <typename P>
+  P *at(size_t off) const { return reinterpret_cast<P *>(ws + off); }
+};
+
+namespace {
+
+lbm3_status hip_fail(lbm3_ctx *c, hipError_t e, const char *what) {
+  if (c) {
+    char b[256];
+    snprintf(b, sizeof b, "%s: %s", what, hipGetErrorString(e));
+    c->err = b;
+  }
+  return LBM3_EHIP;
+}
+
+#define HIPC(c, call)                                      \
+  do {                                                     \
+    hipError_t e_ = (call);                                \
+    if (e_ != hipSuccess) return hip_fail(c, e_, #call);   \
+  } while (0)
+
+void build_work(lbm3_ctx *c) {
+  c->work.clear();
+  for (int d = 0; d < c->n; ++d) {
+    DomainDev &D = c->doms[d];
+    D.work_off = (int)c->work.size();
+    for (int y = 0; y < D.ny; y += c->ty)
+      for (int x = 0; x < D.nx; x += c->tx) c->work.push_back(WorkItem{d, x, y, 0});
+    D.n_work = (int)c->work.size() - D.work_off;
+  }
+}
+
+lbm3_status upload_tables(lbm3_ctx *c) {
+  HIPC(c, hipMemcpyAsync(c->at<void>(c->L.off_doms), c->doms.data(), sizeof(DomainDev) * c->n, hipMemcpyHostToDevice, c->stream));
+  HIPC(c, hipMemcpyAsync(c->at<void>(c->L.off_work), c->work.data(), sizeof(WorkItem) * c->work.size(), hipMemcpyHostToDevice, c->stream));
+  HIPC(c, hipStreamSynchronize(c->stream));
+  return LBM3_OK;
+}
+
+template <typename S, typename T>
+StepArgs<S, T> step_args(lbm3_ctx *c, int from) {
+  StepArgs<S, T> a;
+  a.doms = c->at<DomainDev>(c->L.off_doms);
+  a.work = c->at<WorkItem>(c->L.off_work);
+  a.work_begin = 0;
+  a.work_end = (int)c->work.size();
+  a.flags = c->at<uint8_t>(c->L.off_flags);
+  a.ibb = c->at<IbbNode>(c->L.off_ibb);
+  a.fin = c->at<S>(c->L.off_F[from]);
+  a.rin = c->at<T>(c->L.off_R[from]);
+  a.fout = c->at<S>(c->L.off_F[1 - from]);
+  a.rout = c->at<T>(c->L.off_R[1 - from]);
+  a.tile_x = c->tx;
+  a.tile_y = c->ty;
+  a.eps_g = sizeof(T) == 8 ? T(1e-12) : T(1e-7);
+  a.out_rho = a.out_u = a.out_force = nullptr;
+  return a;
+}
+
+template <typename T>
+FillArgs<T> fill_args(lbm3_ctx *c, int which) {
+  FillArgs<T> f;
+  f.fill = c->at<FillNode>(c->L.off_fill);
+  f.n_fill = c->L.n_fill;
+  f.doms = c->at<DomainDev>(c->L.off_doms);
+  f.flags = c->at<uint8_t>(c->L.off_flags);
+  f.rho = c->at<T>(c->L.off_R[which]);
+  return f;
+}
+
+template <typename S, typename T>
+lbm3_status enqueue_steps_t(lbm3_ctx *c, int nsteps, hipStream_t s, hipEvent_t *ev) {
+  const int grid = c->persistent > 0 ? std::min(c->persistent, (int)c->work.size()) : (int)c->work.size();
+  for (int k = 0; k < nsteps; ++k) {
+    if (ev) HIPC(c, hipEventRecord(ev[3 * k], s));
+    HIPC(c, launch_fill<T>(fill_args<T>(c, c->cur), s));
+    if (ev) HIPC(c, hipEventRecord(ev[3 * k + 1], s));
+    HIPC(c, (launch_step<S, T>(step_args<S, T>(c, c->cur), grid, false, s)));
+    if (ev) HIPC(c, hipEventRecord(ev[3 * k + 2], s));
+    c->cur = 1 - c->cur;
+  }
+  return LBM3_OK;
+}
+
+lbm3_status enqueue_steps(lbm3_ctx *c, int nsteps, hipStream_t s, hipEvent_t *ev = nullptr) {
+  switch (c->precision) {
+    case LBM3_F64: return enqueue_steps_t<double, double>(c, nsteps, s, ev);
+    case LBM3_F32: return enqueue_steps_t<float, float>(c, nsteps, s, ev);
+    default: return enqueue_steps_t<__half, float>(c, nsteps, s, ev);
+  }
+}
+
+lbm3_status build_graph(lbm3_ctx *c) {
+  if (c->graph) {
+    (void)hipGraphExecDestroy(c->graph);
+    c->graph = nullptr;
+  }
+  const int saved = c->cur;
+  hipGraph_t g = nullptr;
+  HIPC(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+  lbm3_status st = enqueue_steps(c, c->graph_block, c->cap_stream);
+  hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+  c->cur = saved;
+  if (st != LBM3_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "hipStreamEndCapture");
+  e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return hip_fail(c, e, "hipGraphInstantiate");
+  c->graph_valid = true;
+  return LBM3_OK;
+}
+
+template <typename S, typename T>
+void init_state(const lbm3_domain *d, int n, const std::vector<DomHost> &H, int64_t total,
+                std::vector<unsigned char> &Fh, std::vector<unsigned char> &Rh) {
+  Fh.assign(9 * (size_t)total * sizeof(S), 0);
+  Rh.assign(3 * (size_t)total * sizeof(T), 0);
+  S *F = reinterpret_cast<S *>(Fh.data());
+  T *R = reinterpret_cast<T *>(Rh.data());
+  const double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+  for (int dd = 0; dd < n; ++dd) {
+    const DomainDev &D = H[dd].dd;
+    const size_t np = (size_t)d[dd].nx * d[dd].ny;
+    for (int j = 0; j < D.ny; ++j)
+      for (int i = 0; i < D.nx; ++i) {
+        const int64_t li = plane_index(i, j, D.pitch);
+        if (H[dd].flags[li] & FL_SOLID) continue;
+        const size_t src = (size_t)j * D.nx + i;
+        const double r0 = d[dd].rho_init[src], r1 = d[dd].rho_init[np + src], r2 = d[dd].rho_init[2 * np + src];
+        const double rho = r0 + r1 + r2;
+        for (int a = 0; a < 9; ++a) {
+          const double v = (rho - 1.0) * w[a];  // shifted f = rho w_a - w_a at rest
+          if constexpr (sizeof(S) == 2) F[9 * D.base + a * D.plane + li] = __float2half_rn((float)v);
+          else F[9 * D.base + a * D.plane + li] = (S)v;
+        }
+        R[3 * D.base + li] = (T)r0;
+        R[3 * D.base + D.plane + li] = (T)r1;
+        R[3 * D.base + 2 * D.plane + li] = (T)r2;
+      }
+  }
+}
+
+template <typename S, typename T>
+lbm3_status fields_t(lbm3_ctx *c, int dom, void *rho, void *u, void *force) {
+  HIPC(c, launch_fill<T>(fill_args<T>(c, c->cur), c->stream));
+  StepArgs<S, T> a = step_args<S, T>(c, c->cur);
+  a.work_begin = c->doms[dom].work_off;
+  a.work_end = c->doms[dom].work_off + c->doms[dom].n_work;
+  a.out_rho = reinterpret_cast<T *>(rho);
+  a.out_u = reinterpret_cast<T *>(u);
+  a.out_force = reinterpret_cast<T *>(force);
+  HIPC(c, (launch_step<S, T>(a, c->doms[dom].n_work, true, c->stream)));
+  return LBM3_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *lbm3_status_string(int32_t code) {
+  switch (code) {
+    case LBM3_OK: return "ok";
+    case LBM3_EINVAL: return "invalid argument";
+    case LBM3_ENOMEM: return "out of memory / workspace too small";
+    case LBM3_EHIP: return "HIP runtime error";
+    case LBM3_ESTATE: return "invalid state";
+    case LBM3_ENUMERIC: return "non-finite density";
+    case LBM3_EUNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+  }
+}
+
+const char *lbm3_last_error(const lbm3_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+static thread_local std::string g_plan_err;
+
+lbm3_status lbm3_workspace_bytes(const lbm3_domain *d, int32_t n, const lbm3_options *o, size_t *bytes) {
+  if (!bytes) return LBM3_EINVAL;
+  std::vector<DomHost> H;
+  Layout L;
+  if (!plan(d, n, o, H, L, g_plan_err)) return LBM3_EINVAL;
+  *bytes = L.total;
+  return LBM3_OK;
+}
+
+lbm3_status lbm3_create(const lbm3_domain *d, int32_t n, const lbm3_options *o, void *dev_workspace,
+                        size_t bytes, void *hip_stream, lbm3_ctx **out) {
+  if (!out) return LBM3_EINVAL;
+  *out = nullptr;
+  std::vector<DomHost> H;
+  Layout L;
+  if (!plan(d, n, o, H, L, g_plan_err)) return LBM3_EINVAL;
+  if (!dev_workspace || bytes < L.total) {
+    g_plan_err = "workspace missing or smaller than lbm3_workspace_bytes";
+    return LBM3_ENOMEM;
+  }
+  if ((reinterpret_cast<uintptr_t>(dev_workspace) & 255) != 0) {
+    g_plan_err = "workspace must be 256-byte aligned";
+    return LBM3_EINVAL;
+  }
+  lbm3_ctx *c = new lbm3_ctx();
+  c->n = n;
+  c->precision = o->precision;
+  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  c->L = L;
+  c->ws = reinterpret_cast<char *>(dev_workspace);
+  c->graph_block = o->graph_block_steps > 0 ? round_up(o->graph_block_steps, 2) : 0;
+  c->persistent = o->persistent_blocks;
+  if (o->tile_x > 0 && o->tile_y > 0) {
+    c->tx = o->tile_x;
+    c->ty = o->tile_y;
+  } else {
+    c->tx = 64;
+    c->ty = o->precision == LBM3_F64 ? 4 : 8;
+  }
+  if (c->tx * c->ty < kMinTileArea || c->tx * c->ty > 4096 ||
+      step_smem_bytes(c->precision, c->tx, c->ty) > 160 * 1024) {
+    g_plan_err = "tile shape out of range (area 256..4096, LDS <= 160 KiB)";
+    delete c;
+    return LBM3_EINVAL;
+  }
+  for (auto &h : H) c->doms.push_back(h.dd);
+  auto bail = [&](lbm3_status s) {
+    g_plan_err = c->err;
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    delete c;
+    return s;
+  };
+  hipError_t e = init_kernel_attributes();
+  if (e != hipSuccess) return bail(hip_fail(c, e, "hipFuncSetAttribute"));
+  e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
+  if (e != hipSuccess) return bail(hip_fail(c, e, "hipStreamCreateWithFlags"));
+  build_work(c);
+  // chunk tables of the mass reduction
+  std::vector<int> chunk_dom, chunk_first;
+  for (int i = 0; i < n; ++i) {
+    chunk_first.push_back((int)chunk_dom.size());
+    for (int j = 0; j < d[i].ny; j += 16) chunk_dom.push_back(i);
+  }
+  chunk_first.push_back((int)chunk_dom.size());
+  std::vector<FillNode> fill;
+  std::vector<IbbNode> ibb;
+  std::vector<uint8_t> flags((size_t)L.total_plane);
+  for (int i = 0; i < n; ++i) {
+    fill.insert(fill.end(), H[i].fill.begin(), H[i].fill.end());
+    ibb.insert(ibb.end(), H[i].ibb.begin(), H[i].ibb.end());
+    memcpy(flags.data() + H[i].dd.base, H[i].flags.data(), H[i].flags.size());
+  }
+  std::vector<unsigned char> Fh, Rh;
+  if (c->precision == LBM3_F64) init_state<double, double>(d, n, H, L.total_plane, Fh, Rh);
+  else if (c->precision == LBM3_F32) init_state<float, float>(d, n, H, L.total_plane, Fh, Rh);
+  else init_state<__half, float>(d, n, H, L.total_plane, Fh, Rh);
+  hipStream_t s = c->stream;
+#define CK(call)                                              \
+  do {                                                        \
+    hipError_t e2 = (call);                                   \
+    if (e2 != hipSuccess) return bail(hip_fail(c, e2, #call)); \
+  } while (0)
+  for (int b = 0; b < 2; ++b) {
+    CK(hipMemsetAsync(c->at<void>(L.off_F[b]), 0, Fh.size(), s));
+    CK(hipMemsetAsync(c->at<void>(L.off_R[b]), 0, Rh.size(), s));
+  }
+  CK(hipMemcpyAsync(c->at<void>(L.off_F[0]), Fh.data(), Fh.size(), hipMemcpyHostToDevice, s));
+  CK(hipMemcpyAsync(c->at<void>(L.off_R[0]), Rh.data(), Rh.size(), hipMemcpyHostToDevice, s));
+  CK(hipMemcpyAsync(c->at<void>(L.off_flags), flags.data(), flags.size(), hipMemcpyHostToDevice, s));
+  if (!fill.empty()) CK(hipMemcpyAsync(c->at<void>(L.off_fill), fill.data(), sizeof(FillNode) * fill.size(), hipMemcpyHostToDevice, s));
+  if (!ibb.empty()) CK(hipMemcpyAsync(c->at<void>(L.off_ibb), ibb.data(), sizeof(IbbNode) * ibb.size(), hipMemcpyHostToDevice, s));
+  CK(hipMemcpyAsync(c->at<void>(L.off_chunk_dom), chunk_dom.data(), sizeof(int) * chunk_dom.size(), hipMemcpyHostToDevice, s));
+  CK(hipMemcpyAsync(c->at<void>(L.off_chunk_first), chunk_first.data(), sizeof(int) * chunk_first.size(), hipMemcpyHostToDevice, s));
+  CK(hipMemsetAsync(c->at<void>(L.off_bad), 0, sizeof(int), s));
+#undef CK
+  lbm3_status st = upload_tables(c);  // synchronises the stream
+  if (st != LBM3_OK) return bail(st);
+  *out = c;
+  return LBM3_OK;
+}
+
+lbm3_status lbm3_step(lbm3_ctx *c, int32_t nsteps) {
+  if (!c) return LBM3_EINVAL;
+  if (nsteps < 0) {
+    c->err = "nsteps must be >= 0";
+    return LBM3_EINVAL;
+  }
+  int left = nsteps;
+  if (c->graph_block > 0 && left >= c->graph_block) {
+    if (c->cur == 1) {
+      lbm3_status st = enqueue_steps(c, 1, c->stream);
+      if (st != LBM3_OK) return st;
+      --left;
+    }
+    if (!c->graph_valid) {
+      lbm3_status st = build_graph(c);
+      if (st != LBM3_OK) return st;
+    }
+    while (left >= c->graph_block) {
+      HIPC(c, hipGraphLaunch(c->graph, c->stream));
+      left -= c->graph_block;
+    }
+  }
+  lbm3_status st = enqueue_steps(c, left, c->stream);
+  if (st != LBM3_OK) return st;
+  c->steps += nsteps;
+  return LBM3_OK;
+}
+
+lbm3_status lbm3_fill(lbm3_ctx *c) {
+  if (!c) return LBM3_EINVAL;
+  if (c->precision == LBM3_F64) HIPC(c, launch_fill<double>(fill_args<double>(c, c->cur), c->stream));
+  else HIPC(c, launch_fill<float>(fill_args<float>(c, c->cur), c->stream));
+  return LBM3_OK;
+}
+
+lbm3_status lbm3_fields(lbm3_ctx *c, int32_t domain, void *dev_rho, void *dev_u, void *dev_force, int32_t dtype) {
+  if (!c) return LBM3_EINVAL;
+  if (domain < 0 || domain >= c->n || !dev_rho) {
+    c->err = "bad domain index or missing density buffer";
+    return LBM3_EINVAL;
+  }
+  const int want = c->precision == LBM3_F64 ? LBM3_F64 : LBM3_F32;
+  if (dtype != want) {
+    c->err = "fields are written in the compute type (LBM3_F64 for FP64 contexts, LBM3_F32 otherwise)";
+    return LBM3_EUNSUPPORTED;
+  }
+  switch (c->precision) {
+    case LBM3_F64: return fields_t<double, double>(c, domain, dev_rho, dev_u, dev_force);
+    case LBM3_F32: return fields_t<float, float>(c, domain, dev_rho, dev_u, dev_force);
+    default: return fields_t<__half, float>(c, domain, dev_rho, dev_u, dev_force);
+  }
+}
+
+lbm3_status lbm3_mass(lbm3_ctx *c, double *host_out) {
+  if (!c || !host_out) return LBM3_EINVAL;
+  HIPC(c, hipMemsetAsync(c->at<void>(c->L.off_bad), 0, sizeof(int), c->stream));
+  double *out = c->at<double>(c->L.off_mass);
+  if (c->precision == LBM3_F64) {
+    MassArgs<double> a{c->at<DomainDev>(c->L.off_doms), c->at<uint8_t>(c->L.off_flags), c->at<double>(c->L.off_R[c->cur]),
+                       c->at<int>(c->L.off_chunk_dom), c->at<int>(c->L.off_chunk_first), c->at<double>(c->L.off_partial),
+                       c->at<int>(c->L.off_bad)};
+    HIPC(c, launch_mass<double>(a, c->L.n_chunks, c->n, out, c->stream));
+  } else {
+    MassArgs<float> a{c->at<DomainDev>(c->L.off_doms), c->at<uint8_t>(c->L.off_flags), c->at<float>(c->L.off_R[c->cur]),
+                      c->at<int>(c->L.off_chunk_dom), c->at<int>(c->L.off_chunk_first), c->at<double>(c->L.off_partial),
+                      c->at<int>(c->L.off_bad)};
+    HIPC(c, launch_mass<float>(a, c->L.n_chunks, c->n, out, c->stream));
+  }
+  int bad = 0;
+  HIPC(c, hipMemcpyAsync(host_out, out, sizeof(double) * 3 * c->n, hipMemcpyDeviceToHost, c->stream));
+  HIPC(c, hipMemcpyAsync(&bad, c->at<void>(c->L.off_bad), sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPC(c, hipStreamSynchronize(c->stream));
+  if (bad) {
+    c->err = "non-finite partial density found";
+    return LBM3_ENUMERIC;
+  }
+  return LBM3_OK;
+}
+
+lbm3_status lbm3_state_bytes(const lbm3_ctx *c, size_t *bytes) {
+  if (!c || !bytes) return LBM3_EINVAL;
+  *bytes = 9 * (size_t)c->L.total_plane * s_size(c->precision) + 3 * (size_t)c->L.total_plane * t_size(c->precision);
+  return LBM3_OK;
+}
+
+lbm3_status lbm3_get_state(lbm3_ctx *c, void *dev_dst) {
+  if (!c || !dev_dst) return LBM3_EINVAL;
+  const size_t fb = 9 * (size_t)c->L.total_plane * s_size(c->precision);
+  const size_t rb = 3 * (size_t)c->L.total_plane * t_size(c->precision);
+  char *d = reinterpret_cast<char *>(dev_dst);
+  HIPC(c, hipMemcpyAsync(d, c->at<void>(c->L.off_F[c->cur]), fb, hipMemcpyDeviceToDevice, c->stream));
+  HIPC(c, hipMemcpyAsync(d + fb, c->at<void>(c->L.off_R[c->cur]), rb, hipMemcpyDeviceToDevice, c->stream));
+  return LBM3_OK;
+}
+
+lbm3_status lbm3_set_state(lbm3_ctx *c, const void *dev_src) {
+  if (!c || !dev_src) return LBM3_EINVAL;
+  const size_t fb = 9 * (size_t)c->L.total_plane * s_size(c->precision);
+  const size_t rb = 3 * (size_t)c->L.total_plane * t_size(c->precision);
+  const char *s = reinterpret_cast<const char *>(dev_src);
+  HIPC(c, hipMemcpyAsync(c->at<void>(c->L.off_F[c->cur]), s, fb, hipMemcpyDeviceToDevice, c->stream));
+  HIPC(c, hipMemcpyAsync(c->at<void>(c->L.off_R[c->cur]), s + fb, rb, hipMemcpyDeviceToDevice, c->stream));
+  return LBM3_OK;
+}
+
+lbm3_status lbm3_kernel_times(lbm3_ctx *c, int32_t nsteps, double *ms_fill, double *ms_step) {
+  if (!c || nsteps < 1 || !ms_fill || !ms_step) return LBM3_EINVAL;
+  std::vector<hipEvent_t> ev(3 * nsteps, nullptr);
+  for (auto &e : ev) HIPC(c, hipEventCreate(&e));
+  lbm3_status st = enqueue_steps(c, nsteps, c->stream, ev.data());
+  double tf = 0, ts = 0;
+  if (st == LBM3_OK) {
+    hipError_t e = hipEventSynchronize(ev.back());
+    if (e != hipSuccess) st = hip_fail(c, e, "hipEventSynchronize");
+    for (int k = 0; k < nsteps && st == LBM3_OK; ++k) {
+      float a = 0, b = 0;
+      (void)hipEventElapsedTime(&a, ev[3 * k], ev[3 * k + 1]);
+      (void)hipEventElapsedTime(&b, ev[3 * k + 1], ev[3 * k + 2]);
+      tf += a;
+      ts += b;
+    }
+    c->steps += nsteps;
+  }
+  for (auto &e : ev) (void)hipEventDestroy(e);
+  *ms_fill = tf / nsteps;
+  *ms_step = ts / nsteps;
+  return st;
+}
+
+lbm3_status lbm3_autotune(lbm3_ctx *c, int32_t steps_per_candidate, int32_t *tile_xy) {
+  if (!c || steps_per_candidate < 1) return LBM3_EINVAL;
+  const int otx = c->tx, oty = c->ty;
+  double best = 1e300;
+  int btx = otx, bty = oty;
+  for (const TileShape &t : kTiles) {
+    if (t.tx * t.ty < kMinTileArea || step_smem_bytes(c->precision, t.tx, t.ty) > 160 * 1024) continue;
+    c->tx = t.tx;
+    c->ty = t.ty;
+    build_work(c);
+    lbm3_status st = upload_tables(c);
+    if (st != LBM3_OK) return st;
+    double mf, ms;
+    enqueue_steps(c, 2, c->stream);  // warm-up
+    c->steps += 2;
+    st = lbm3_kernel_times(c, steps_per_candidate, &mf, &ms);
+    if (st != LBM3_OK) return st;
+    if (ms < best) {
+      best = ms;
+      btx = t.tx;
+      bty = t.ty;
+    }
+  }
+  c->tx = btx;
+  c->ty = bty;
+  build_work(c);
+  c->graph_valid = false;
+  lbm3_status st = upload_tables(c);
+  if (st != LBM3_OK) return st;
+  if (tile_xy) {
+    tile_xy[0] = btx;
+    tile_xy[1] = bty;
+  }
+  return LBM3_OK;
+}
+
+lbm3_status lbm3_query(const lbm3_ctx *c, int32_t key, double *value) {
+  if (!c || !value) return LBM3_EINVAL;
+  int64_t nodes = 0;
+  for (const auto &D : c->doms) nodes += (int64_t)D.nx * D.ny;
+  switch (key) {
+    case 0: *value = 2.0 * (9.0 * s_size(c->precision) + 3.0 * t_size(c->precision)); break;
+    case 1: *value = (double)nodes; break;
+    case 2: *value = c->L.n_fill; break;
+    case 3: *value = c->L.n_ibb; break;
+    case 4: *value = c->tx; break;
+    case 5: *value = c->ty; break;
+    case 6: *value = (double)c->work.size(); break;
+    case 7: *value = (double)c->steps; break;
+    default: return LBM3_EINVAL;
+  }
+  return LBM3_OK;
+}
+
+const char *lbm3_plan_error(void) { return g_plan_err.c_str(); }
+
+void lbm3_destroy(lbm3_ctx *c) {
+  if (!c) return;
+  if (c->graph) (void)hipGraphExecDestroy(c->graph);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  delete c;
+}
+
+}  // extern "C"

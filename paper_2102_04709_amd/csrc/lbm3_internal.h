@@ -1,0 +1,148 @@
+// lbm3_internal.h -- device layout and helpers shared by the host set-up and the gfx950
+// kernels of liblbm3 (never by the CPU checker).
+//
+// Data layout in HBM, per domain d with plane size P_d = pitch_d * (ny_d + 4):
+//   distributions : 9 planes of storage type S, the shift f_a - w_a (rho^0 = 1)
+//   densities     : 3 planes of compute type T, the partial densities rho_k at fluid nodes and
+//                   the filled mass fractions C_k at the solid boundary nodes
+//   flags         : 1 plane of uint8
+// A plane holds rows -2 .. ny+1 (two padding rows on each side hold the off-grid solid layers
+// of a non-periodic y boundary); row j starts at element pitch*(j+2).  All domains' planes
+// are concatenated: domain d starts at element base_d = sum of P over the earlier domains
+// (times 9 for the distributions and 3 for the densities).  x is the fastest index, so a
+// wavefront reads 64 consecutive nodes of one row.
+#pragma once
+
+#include <stdint.h>
+
+#ifndef __HIPCC__
+#define __host__
+#define __device__
+#endif
+
+namespace lbm3 {
+
+constexpr int kThreads = 256;  // work-group size of every kernel
+
+enum : uint8_t {
+  FL_SOLID = 1,   // solid node (mask, or off-grid row of a non-periodic y boundary)
+  FL_FILL = 2,    // solid node whose C is filled by the wetting condition (C_SB or C_SB2)
+  FL_CURVED = 4,  // fluid node with at least one interpolated-bounce-back link
+};
+
+enum { BCX_PERIODIC = 0, BCX_SWAP13 = 1, BCX_ZOUHE = 2 };
+
+// Per-domain constants, in device memory.
+struct DomainDev {
+  int32_t nx, ny, pitch, yper;
+  int32_t bcx, n_fill, fill_off, n_ibb;
+  int32_t ibb_off, work_off, n_work, pad_;
+  int64_t base;   // element offset of plane 0 of this domain (before the x9 / x3 factors)
+  int64_t plane;  // P = pitch * (ny + 4)
+  double u_in, rho_out;
+  double nu[3];
+  double sig[3];   // sigma12, sigma13, sigma23
+  double gX[3];    // g(X_kl) of Eq. (15) for the pairs 12, 13, 23
+  double beta0;
+  double th13, th23, th12;  // radians
+  double g[2];     // body acceleration
+};
+
+// A solid node whose C is filled (C_SB or C_SB2), with its fluid-pointing unit normal.
+struct FillNode {
+  int32_t dom, i, j, li;  // domain, coordinates, index within the domain's plane
+  double nx, ny;
+};
+
+// A fluid node with interpolated-bounce-back links: q[a-1] for direction a = 1..8 is the
+// fraction of the link from the node towards x - e_a at which the wall lies (1/2 when the link
+// is not cut by a circle).
+struct IbbNode {
+  int32_t li, dom;
+  double q[8];
+};
+
+struct WorkItem {
+  int32_t dom, x0, y0, pad_;
+};
+
+__host__ __device__ inline int64_t plane_index(int i, int j, int pitch) {
+  return (int64_t)i + (int64_t)pitch * (j + 2);
+}
+
+// ---- characteristic line (Sec. II B) ------------------------------------------------------
+// From node (pi, pj) along (dx, dy), t > 0, visit the crossings with the vertical lines
+// x = integer and the horizontal lines y = integer in increasing t.  At a horizontal line the
+// two nodes left and right of the crossing are interpolated, at a vertical line the two nodes
+// below and above; a crossing within 1e-9 of a node uses that node alone.  The first crossing
+// whose nodes are all fluid is the intersection point D; beyond t = 24 the line fails.
+constexpr double kEpsDir = 1e-12;
+constexpr double kEpsNode = 1e-9;
+constexpr double kTMax = 24.0;
+
+struct LineHit {
+  int ok;
+  int i0, j0, i1, j1;  // interpolation nodes (equal for a node hit)
+  double w;            // value = v(i0, j0) + w * (v(i1, j1) - v(i0, j0))
+};
+
+template <class FluidAt>
+__host__ __device__ inline LineHit march_line(int pi, int pj, double dx, double dy,
+                                              const FluidAt &fluid) {
+  LineHit h;
+  h.ok = 0;
+  h.i0 = h.j0 = h.i1 = h.j1 = 0;
+  h.w = 0.0;
+  const int sx = dx > kEpsDir ? 1 : (dx < -kEpsDir ? -1 : 0);
+  const int sy = dy > kEpsDir ? 1 : (dy < -kEpsDir ? -1 : 0);
+  const double ax = dx < 0 ? -dx : dx, ay = dy < 0 ? -dy : dy;
+  int kx = 1, ky = 1;
+  for (int guard = 0; guard < 256; ++guard) {
+    const double tx = sx ? (double)kx / ax : 1e300;
+    const double ty = sy ? (double)ky / ay : 1e300;
+    const double t = tx < ty ? tx : ty;
+    if (t > kTMax) return h;
+    if (tx <= ty) {
+      const int i = pi + sx * kx;
+      const double y = pj + tx * dy;
+      const double yr = floor(y + 0.5);
+      ++kx;
+      if (fabs(y - yr) < kEpsNode) {
+        const int j = (int)yr;
+        if (sy && j == pj + sy * ky) ++ky;
+        if (fluid(i, j)) {
+          h.ok = 1; h.i0 = h.i1 = i; h.j0 = h.j1 = j; h.w = 0.0;
+          return h;
+        }
+      } else {
+        const int j0 = (int)floor(y);
+        if (fluid(i, j0) && fluid(i, j0 + 1)) {
+          h.ok = 1; h.i0 = h.i1 = i; h.j0 = j0; h.j1 = j0 + 1; h.w = y - j0;
+          return h;
+        }
+      }
+    } else {
+      const int j = pj + sy * ky;
+      const double x = pi + ty * dx;
+      const double xr = floor(x + 0.5);
+      ++ky;
+      if (fabs(x - xr) < kEpsNode) {
+        const int i = (int)xr;
+        if (sx && i == pi + sx * kx) ++kx;
+        if (fluid(i, j)) {
+          h.ok = 1; h.i0 = h.i1 = i; h.j0 = h.j1 = j; h.w = 0.0;
+          return h;
+        }
+      } else {
+        const int i0 = (int)floor(x);
+        if (fluid(i0, j) && fluid(i0 + 1, j)) {
+          h.ok = 1; h.i0 = i0; h.i1 = i0 + 1; h.j0 = h.j1 = j; h.w = x - i0;
+          return h;
+        }
+      }
+    }
+  }
+  return h;
+}
+
+}  // namespace lbm3

@@ -1,0 +1,58 @@
+// lbm3_kernels.h -- argument blocks and launchers of the gfx950 kernels (internal to liblbm3).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "lbm3_internal.h"
+
+namespace lbm3 {
+
+template <typename T>
+struct FillArgs {
+  const FillNode *fill;
+  int n_fill;
+  const DomainDev *doms;
+  const uint8_t *flags;
+  T *rho;  // density planes of the current state (read at fluid nodes, written at fill nodes)
+};
+
+template <typename S, typename T>
+struct StepArgs {
+  const DomainDev *doms;
+  const WorkItem *work;
+  int work_begin, work_end;
+  const uint8_t *flags;
+  const IbbNode *ibb;
+  const S *fin;
+  const T *rin;
+  S *fout;
+  T *rout;
+  int tile_x, tile_y;
+  T eps_g;
+  // fields mode only: [comp][ny][nx] outputs of one domain
+  T *out_rho, *out_u, *out_force;
+};
+
+template <typename T>
+struct MassArgs {
+  const DomainDev *doms;
+  const uint8_t *flags;
+  const T *rho;
+  const int *chunk_dom;    // [n_chunks]
+  const int *chunk_first;  // [n_dom + 1]
+  double *partial;         // [3 * n_chunks]
+  int *bad;
+};
+
+template <typename T>
+hipError_t launch_fill(const FillArgs<T> &a, hipStream_t s);
+template <typename S, typename T>
+hipError_t launch_step(const StepArgs<S, T> &a, int grid, bool fields, hipStream_t s);
+template <typename T>
+hipError_t launch_mass(const MassArgs<T> &a, int n_chunks, int n_dom, double *out, hipStream_t s);
+size_t step_smem_bytes(int precision, int tx, int ty);
+hipError_t init_kernel_attributes();
+
+}  // namespace lbm3

@@ -1,0 +1,293 @@
+"""Thin Python binding of liblbm3 (include/lbm3.h): argument marshalling only.
+
+Every step of the lattice update runs in the HIP kernels of liblbm3.so; PyTorch supplies the
+device memory (the workspace and field buffers) and the stream.  There is no CPU fallback:
+if the library is missing, loading it raises.
+
+The module-level functions carry the C names; `Simulation` strings them together.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Dict, Iterable, List, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblbm3.so")
+
+LBM3_OK, LBM3_EINVAL, LBM3_ENOMEM, LBM3_EHIP, LBM3_ESTATE, LBM3_ENUMERIC, LBM3_EUNSUPPORTED = range(7)
+LBM3_F64, LBM3_F32, LBM3_F32_STORE_F16 = 0, 1, 2
+PRECISIONS = {"f64": LBM3_F64, "f32": LBM3_F32, "f16": LBM3_F32_STORE_F16}
+
+# Symbols declared in include/lbm3.h.
+ABI_SYMBOLS = [
+    "lbm3_workspace_bytes", "lbm3_create", "lbm3_step", "lbm3_fill", "lbm3_fields", "lbm3_mass",
+    "lbm3_state_bytes", "lbm3_get_state", "lbm3_set_state", "lbm3_kernel_times", "lbm3_autotune",
+    "lbm3_query", "lbm3_last_error", "lbm3_plan_error", "lbm3_status_string", "lbm3_destroy",
+]
+
+
+class lbm3_domain(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int32), ("ny", C.c_int32), ("y_periodic", C.c_int32), ("bc_x", C.c_int32),
+        ("u_in", C.c_double), ("rho_out", C.c_double),
+        ("nu", C.c_double * 3), ("sigma", C.c_double * 3), ("theta_deg", C.c_double * 2),
+        ("body_force", C.c_double * 2),
+        ("n_circles", C.c_int32), ("reserved", C.c_int32),
+        ("circles", C.POINTER(C.c_double)), ("solid", C.POINTER(C.c_uint8)),
+        ("rho_init", C.POINTER(C.c_double)),
+    ]
+
+
+class lbm3_options(C.Structure):
+    _fields_ = [
+        ("precision", C.c_int32), ("graph_block_steps", C.c_int32), ("beta0", C.c_double),
+        ("tile_x", C.c_int32), ("tile_y", C.c_int32), ("persistent_blocks", C.c_int32),
+        ("reserved", C.c_int32),
+    ]
+
+
+class Lbm3Error(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"lbm3 status {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def library() -> C.CDLL:
+    """Loads liblbm3.so (built in-tree by __graft_entry__.build()); raises if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, dp, szp = C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_size_t)
+        dom_p, opt_p = C.POINTER(lbm3_domain), C.POINTER(lbm3_options)
+        sig = {
+            "lbm3_workspace_bytes": (i32, [dom_p, i32, opt_p, szp]),
+            "lbm3_create": (i32, [dom_p, i32, opt_p, vp, C.c_size_t, vp, C.POINTER(vp)]),
+            "lbm3_step": (i32, [vp, i32]),
+            "lbm3_fill": (i32, [vp]),
+            "lbm3_fields": (i32, [vp, i32, vp, vp, vp, i32]),
+            "lbm3_mass": (i32, [vp, dp]),
+            "lbm3_state_bytes": (i32, [vp, szp]),
+            "lbm3_get_state": (i32, [vp, vp]),
+            "lbm3_set_state": (i32, [vp, vp]),
+            "lbm3_kernel_times": (i32, [vp, i32, dp, dp]),
+            "lbm3_autotune": (i32, [vp, i32, C.POINTER(C.c_int32)]),
+            "lbm3_query": (i32, [vp, i32, dp]),
+            "lbm3_last_error": (C.c_char_p, [vp]),
+            "lbm3_plan_error": (C.c_char_p, []),
+            "lbm3_status_string": (C.c_char_p, [i32]),
+            "lbm3_destroy": (None, [vp]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+class DomainArgs:
+    """lbm3_domain structs for a list of workloads, keeping the host arrays alive."""
+
+    def __init__(self, workloads: Sequence):
+        self.keep: List[np.ndarray] = []
+        arr = (lbm3_domain * len(workloads))()
+        for d, w in zip(arr, workloads):
+            solid = np.ascontiguousarray(w.solid, dtype=np.uint8)
+            rho = np.ascontiguousarray(w.rho_init, dtype=np.float64)
+            circ = np.ascontiguousarray(np.asarray(w.circles, dtype=np.float64).reshape(-1))
+            self.keep += [solid, rho, circ]
+            d.nx, d.ny, d.y_periodic, d.bc_x = w.nx, w.ny, w.y_periodic, w.bc_x
+            d.u_in, d.rho_out = w.u_in, w.rho_out
+            for k in range(3):
+                d.nu[k] = w.nu[k]
+                d.sigma[k] = w.sigma[k]
+            d.theta_deg[0], d.theta_deg[1] = w.theta_deg
+            d.body_force[0], d.body_force[1] = w.body_force
+            d.n_circles = circ.size // 3
+            d.reserved = 0
+            d.circles = circ.ctypes.data_as(C.POINTER(C.c_double)) if circ.size else None
+            d.solid = solid.ctypes.data_as(C.POINTER(C.c_uint8))
+            d.rho_init = rho.ctypes.data_as(C.POINTER(C.c_double))
+        self.array = arr
+        self.n = len(workloads)
+
+
+def make_options(precision="f32", graph_block_steps=0, beta0=0.0, tile=None, persistent_blocks=0):
+    o = lbm3_options()
+    o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    o.graph_block_steps = int(graph_block_steps)
+    o.beta0 = float(beta0)
+    o.tile_x, o.tile_y = (0, 0) if tile is None else (int(tile[0]), int(tile[1]))
+    o.persistent_blocks = int(persistent_blocks)
+    o.reserved = 0
+    return o
+
+
+def _check(code: int, ctx=None) -> None:
+    if code != LBM3_OK:
+        L = library()
+        msg = (L.lbm3_last_error(ctx) if ctx else L.lbm3_plan_error()) or b""
+        raise Lbm3Error(code, msg.decode() or L.lbm3_status_string(code).decode())
+
+
+# ---- the C entry points, one to one ------------------------------------------------------
+
+def lbm3_workspace_bytes(domains: DomainArgs, options: lbm3_options) -> int:
+    n = C.c_size_t(0)
+    _check(library().lbm3_workspace_bytes(domains.array, domains.n, C.byref(options), C.byref(n)))
+    return n.value
+
+
+def lbm3_create(domains: DomainArgs, options: lbm3_options, workspace_ptr: int, nbytes: int, stream_ptr: int):
+    out = C.c_void_p()
+    _check(library().lbm3_create(domains.array, domains.n, C.byref(options), C.c_void_p(workspace_ptr),
+                                 nbytes, C.c_void_p(stream_ptr), C.byref(out)))
+    return out
+
+
+def lbm3_step(ctx, nsteps: int) -> None:
+    _check(library().lbm3_step(ctx, int(nsteps)), ctx)
+
+
+def lbm3_fill(ctx) -> None:
+    _check(library().lbm3_fill(ctx), ctx)
+
+
+def lbm3_fields(ctx, domain: int, rho_ptr: int, u_ptr: int, force_ptr: int, dtype: int) -> None:
+    _check(library().lbm3_fields(ctx, int(domain), C.c_void_p(rho_ptr), C.c_void_p(u_ptr or None),
+                                 C.c_void_p(force_ptr or None), int(dtype)), ctx)
+
+
+def lbm3_mass(ctx, n_domains: int) -> np.ndarray:
+    out = np.zeros(3 * n_domains)
+    _check(library().lbm3_mass(ctx, out.ctypes.data_as(C.POINTER(C.c_double))), ctx)
+    return out.reshape(n_domains, 3)
+
+
+def lbm3_state_bytes(ctx) -> int:
+    n = C.c_size_t(0)
+    _check(library().lbm3_state_bytes(ctx, C.byref(n)), ctx)
+    return n.value
+
+
+def lbm3_get_state(ctx, dst_ptr: int) -> None:
+    _check(library().lbm3_get_state(ctx, C.c_void_p(dst_ptr)), ctx)
+
+
+def lbm3_set_state(ctx, src_ptr: int) -> None:
+    _check(library().lbm3_set_state(ctx, C.c_void_p(src_ptr)), ctx)
+
+
+def lbm3_kernel_times(ctx, nsteps: int):
+    a, b = C.c_double(0), C.c_double(0)
+    _check(library().lbm3_kernel_times(ctx, int(nsteps), C.byref(a), C.byref(b)), ctx)
+    return a.value, b.value
+
+
+def lbm3_autotune(ctx, steps: int):
+    t = (C.c_int32 * 2)()
+    _check(library().lbm3_autotune(ctx, int(steps), t), ctx)
+    return int(t[0]), int(t[1])
+
+
+def lbm3_query(ctx, key: int) -> float:
+    v = C.c_double(0)
+    _check(library().lbm3_query(ctx, int(key), C.byref(v)), ctx)
+    return v.value
+
+
+def lbm3_destroy(ctx) -> None:
+    library().lbm3_destroy(ctx)
+
+
+# ---- convenience wrapper --------------------------------------------------------------------
+
+class Simulation:
+    """Domains advanced together on one GPU by liblbm3."""
+
+    def __init__(self, workloads, precision="f32", graph_block_steps=0, tile=None,
+                 persistent_blocks=0, beta0=0.0, device="cuda:0"):
+        import torch
+
+        if not isinstance(workloads, (list, tuple)):
+            workloads = [workloads]
+        self.workloads = list(workloads)
+        self.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        self.device = torch.device(device)
+        self.domains = DomainArgs(self.workloads)
+        self.options = make_options(precision, graph_block_steps, beta0, tile, persistent_blocks)
+        nbytes = lbm3_workspace_bytes(self.domains, self.options)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        self.ctx = lbm3_create(self.domains, self.options, self.workspace.data_ptr(), nbytes,
+                               self.stream.cuda_stream)
+        self.n = len(self.workloads)
+
+    @property
+    def field_dtype(self):
+        import torch
+        return torch.float64 if self.precision == LBM3_F64 else torch.float32
+
+    def step(self, n: int = 1) -> None:
+        lbm3_step(self.ctx, n)
+
+    def fill(self) -> None:
+        lbm3_fill(self.ctx)
+
+    def fields(self, domain: int = 0, velocity=True, force=True) -> Dict[str, "object"]:
+        import torch
+        w = self.workloads[domain]
+        dt = self.field_dtype
+        rho = torch.empty((3, w.ny, w.nx), dtype=dt, device=self.device)
+        u = torch.empty((2, w.ny, w.nx), dtype=dt, device=self.device) if velocity else None
+        F = torch.empty((2, w.ny, w.nx), dtype=dt, device=self.device) if force else None
+        lbm3_fields(self.ctx, domain, rho.data_ptr(), u.data_ptr() if u is not None else 0,
+                    F.data_ptr() if F is not None else 0,
+                    LBM3_F64 if self.precision == LBM3_F64 else LBM3_F32)
+        out = {"rho": rho}
+        if u is not None:
+            out["u"] = u
+        if F is not None:
+            out["force"] = F
+        return out
+
+    def mass(self) -> np.ndarray:
+        return lbm3_mass(self.ctx, self.n)
+
+    def get_state(self):
+        import torch
+        buf = torch.empty(lbm3_state_bytes(self.ctx), dtype=torch.uint8, device=self.device)
+        lbm3_get_state(self.ctx, buf.data_ptr())
+        return buf
+
+    def set_state(self, buf) -> None:
+        assert buf.numel() == lbm3_state_bytes(self.ctx) and buf.is_contiguous()
+        lbm3_set_state(self.ctx, buf.data_ptr())
+
+    def kernel_times(self, nsteps: int):
+        return lbm3_kernel_times(self.ctx, nsteps)
+
+    def autotune(self, steps: int = 5):
+        return lbm3_autotune(self.ctx, steps)
+
+    def query(self, key: int) -> float:
+        return lbm3_query(self.ctx, key)
+
+    def close(self) -> None:
+        if getattr(self, "ctx", None) is not None:
+            lbm3_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
