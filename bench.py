@@ -44,7 +44,7 @@ def roofline(sim, launches=50):
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
             "kernel": "step_fused", "bytes_per_lup": bpl, "lups_per_launch": int(nodes),
-            "ms_per_launch": round(ms_step, 5), "fill_ms_per_launch": round(ms_fill, 5)}
+            "ms_per_launch": round(ms_step, 5), "fill_kernel_ms_per_launch": round(ms_fill, 5)}
 
 
 def measure(workloads_, precision, steps, warmup, graph=100, tile=None):

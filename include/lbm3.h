@@ -94,11 +94,14 @@ typedef struct {
                                 (rounded up to even); 0: plain launches */
   double beta0;              /* reference segregation parameter of Eq. (14); <= 0 selects the
                                 paper's 0.7 */
-  int32_t tile_x, tile_y;    /* tile of the fused step kernel; 0 selects the default or the
-                                autotuned shape */
+  int32_t kernel;            /* fused-step kernel: 0 = tiles (tile_x x tile_y nodes per
+                                work-group), 1 = row strips of 122 columns (128 threads),
+                                2 = row strips of 250 columns (256 threads); -1 = let
+                                lbm3_autotune choose (tiles until it runs) */
+  int32_t tile_x, tile_y;    /* tiles: the tile shape (0 = default); strips: tile_y = rows per
+                                segment (0 = default), tile_x unused */
   int32_t persistent_blocks; /* > 0: the fused kernel runs this many work-groups that loop over
-                                the (domain, tile) work list; 0: one work-group per tile */
-  int32_t reserved;          /* must be 0 */
+                                the (domain, tile) work list; 0: one work-group per work item */
 } lbm3_options;
 
 /* Bytes of device workspace lbm3_create needs for n domains (d[0..n-1]) and these options. */
@@ -117,18 +120,16 @@ lbm3_status lbm3_create(const lbm3_domain *d, int32_t n, const lbm3_options *o,
 /* Advances every domain by nsteps time steps (asynchronous). */
 lbm3_status lbm3_step(lbm3_ctx *c, int32_t nsteps);
 
-/* Runs only the wetting fill (Eq. 21-22) on the current state, writing C into the solid
- * boundary slots; the next lbm3_step recomputes it.  For stage-by-stage checks. */
-lbm3_status lbm3_fill(lbm3_ctx *c);
-
-/* Writes fields of domain `domain` into caller device buffers of element type dtype
- * (LBM3_F64 -> double, LBM3_F32 -> float), layout [comp][ny][nx]:
- *   dev_rho [3]: partial densities at fluid nodes; at solid boundary nodes the C filled by the
- *                last fill on this state (lbm3_fill), 0 at other solid nodes;
- *   dev_u   [2]: velocity of Eq. (11) including the interfacial force of the current state
- *                (0 at solid nodes); may be NULL;
+/* Writes fields of the current state of domain `domain` into caller device buffers of element
+ * type dtype (LBM3_F64 -> double for FP64 contexts, LBM3_F32 -> float otherwise), layout
+ * [comp][ny][nx]:
+ *   dev_rho [3]: partial densities at fluid nodes; at the solid boundary nodes the mass
+ *                fractions C_k of the wetting fill (Eq. 21-22) of this state, 0 at other solid
+ *                nodes;
+ *   dev_u   [2]: velocity of Eq. (11) including the interfacial force (0 at solid nodes); may
+ *                be NULL;
  *   dev_force [2]: interfacial force of Eq. (10) plus the body force; may be NULL.
- * Runs the fill first.  Asynchronous. */
+ * Asynchronous. */
 lbm3_status lbm3_fields(lbm3_ctx *c, int32_t domain, void *dev_rho, void *dev_u,
                         void *dev_force, int32_t dtype);
 
@@ -142,18 +143,20 @@ lbm3_status lbm3_state_bytes(const lbm3_ctx *c, size_t *bytes);
 lbm3_status lbm3_get_state(lbm3_ctx *c, void *dev_dst);
 lbm3_status lbm3_set_state(lbm3_ctx *c, const void *dev_src);
 
-/* Average device time (ms) of the wetting-fill and fused-step kernels over nsteps plain steps,
- * from HIP events recorded on the context's stream around each launch.  Advances the state by
- * nsteps.  Synchronises. */
+/* Average device time (ms) of one launch of the wetting-fill kernel and of the fused step kernel
+ * over nsteps plain steps, from HIP events recorded on the context's stream around each launch.
+ * Advances the state by nsteps.  Synchronises. */
 lbm3_status lbm3_kernel_times(lbm3_ctx *c, int32_t nsteps, double *ms_fill, double *ms_step);
 
-/* Times the candidate tile shapes of the fused kernel on the current state (restoring it
- * afterwards) and keeps the fastest; returns it in tile_xy[2].  Synchronises. */
-lbm3_status lbm3_autotune(lbm3_ctx *c, int32_t steps_per_candidate, int32_t *tile_xy);
+/* Times the candidate configurations of the fused kernel (tile shapes, strip widths and
+ * segment lengths) on the live state and keeps the fastest; returns (kernel, tile_x, tile_y)
+ * in choice[3].  Every candidate computes the same result bit for bit; timing them advances
+ * the state.  Synchronises. */
+lbm3_status lbm3_autotune(lbm3_ctx *c, int32_t steps_per_candidate, int32_t *choice);
 
 /* Information: key 0 = algorithmic bytes per lattice update of the fused kernel (state read
  * once and written once), 1 = total nodes, 2 = fill nodes, 3 = interpolated-bounce-back nodes,
- * 4 = tile_x, 5 = tile_y, 6 = work items (tiles), 7 = steps taken. */
+ * 4 = tile_x, 5 = tile_y, 6 = work items, 7 = steps taken, 8 = kernel (0 tiles, 1/2 strips). */
 lbm3_status lbm3_query(const lbm3_ctx *c, int32_t key, double *value);
 
 const char *lbm3_last_error(const lbm3_ctx *c);

@@ -33,12 +33,17 @@ const int kEX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
 const int kEY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 const double kPI = 3.14159265358979323846;
 
-struct TileShape {
-  int tx, ty;
+struct Candidate {
+  int kernel, tx, ty;
 };
-// Candidate tiles of the fused kernel (the autotuner picks among them).
-const TileShape kTiles[] = {{32, 8}, {64, 4}, {64, 8}, {32, 16}, {128, 4}, {16, 16}, {64, 16}, {128, 8}};
+// Candidate configurations of the fused kernel (the autotuner picks among them).
+const Candidate kCands[] = {{MODE_TILE, 32, 8},      {MODE_TILE, 64, 4},      {MODE_TILE, 64, 8},
+                            {MODE_TILE, 32, 16},     {MODE_TILE, 16, 16},     {MODE_TILE, 128, 4},
+                            {MODE_STRIP128, 0, 32},  {MODE_STRIP128, 0, 64},  {MODE_STRIP128, 0, 128},
+                            {MODE_STRIP256, 0, 32},  {MODE_STRIP256, 0, 64},  {MODE_STRIP256, 0, 128}};
 const int kMinTileArea = 256;
+const int kMinStripRows = 8;
+const int kFieldTileX = 32, kFieldTileY = 8;  // tile of the field export
 
 int round_up(int v, int m) { return (v + m - 1) / m * m; }
 
@@ -50,10 +55,10 @@ struct DomHost {
 };
 
 struct Layout {
-  size_t off_F[2], off_R[2], off_flags, off_fill, off_ibb, off_doms, off_work, off_partial,
+  size_t off_F[2], off_R[2], off_flags, off_fill, off_fillC, off_ibb, off_doms, off_work, off_fwork, off_partial,
       off_chunk_dom, off_chunk_first, off_mass, off_bad, total;
   int64_t total_plane;
-  int n_fill, n_ibb, n_chunks, max_work;
+  int n_fill, n_ibb, n_chunks, max_work, n_fwork;
 };
 
 size_t s_size(int precision) { return precision == LBM3_F64 ? 8 : (precision == LBM3_F32 ? 4 : 2); }
@@ -214,10 +219,23 @@ bool validate_and_build(const lbm3_domain &d, int dom, double beta0, DomHost &H,
         fn.li = (int32_t)p;
         fn.nx = -(double)sx / len;
         fn.ny = -(double)sy / len;
-        if (!march_line(i, j, fn.nx, fn.ny, fluid_at).ok) {
+        const LineHit h0 = march_line(i, j, fn.nx, fn.ny, fluid_at);
+        if (!h0.ok) {
           snprintf(buf, sizeof buf, "the normal line from solid node (%d,%d) reaches no fluid node", i, j);
           return fail(buf);
         }
+        auto wrapped = [&](int ii, int jj) {
+          if (!zh) ii = ((ii % nx) + nx) % nx;
+          if (yper) jj = ((jj % ny) + ny) % ny;
+          return (int32_t)plane_index(ii, jj, pitch);
+        };
+        fn.d0a = wrapped(h0.i0, h0.j0);
+        fn.d0b = wrapped(h0.i1, h0.j1);
+        fn.d0w = h0.w;
+        fn.mask = 0;
+        for (int dy = -3; dy <= 3; ++dy)
+          for (int dx = -3; dx <= 3; ++dx)
+            if (fluid_at(i + dx, j + dy)) fn.mask |= (uint64_t)1 << ((dy + 3) * 7 + dx + 3);
         H.flags[p] |= FL_FILL;
         H.fill.push_back(fn);
       }
@@ -275,20 +293,21 @@ bool plan(const lbm3_domain *d, int n, const lbm3_options *o, std::vector<DomHos
   if (!d || n < 1) return err = "need at least one domain", false;
   if (!o) return err = "options are required", false;
   if (o->precision < 0 || o->precision > 2) return err = "bad precision", false;
-  if (o->reserved != 0) return err = "reserved must be 0", false;
+  if (o->kernel < -1 || o->kernel > 2) return err = "kernel must be -1, 0, 1 or 2", false;
   if (o->tile_x < 0 || o->tile_y < 0 || o->graph_block_steps < 0 || o->persistent_blocks < 0) return err = "negative option", false;
-  if (o->tile_x > 0 || o->tile_y > 0) {
+  if (o->kernel <= 0 && (o->tile_x > 0 || o->tile_y > 0)) {
     const int area = o->tile_x * o->tile_y;
     if (o->tile_x <= 0 || o->tile_y <= 0 || area < kMinTileArea || area > 4096 ||
-        step_smem_bytes(o->precision, o->tile_x, o->tile_y) > 160 * 1024)
+        step_smem_bytes(o->precision, MODE_TILE, o->tile_x, o->tile_y) > 160 * 1024)
       return err = "tile shape out of range (area 256..4096, LDS <= 160 KiB)", false;
   }
+  if (o->kernel > 0 && o->tile_y > 0 && o->tile_y < kMinStripRows) return err = "strip segments need at least 8 rows", false;
   const double beta0 = o->beta0 > 0 ? o->beta0 : 0.7;
   H.assign(n, DomHost());
   for (int i = 0; i < n; ++i)
     if (!validate_and_build(d[i], i, beta0, H[i], err)) return false;
   int64_t base = 0;
-  int nf = 0, ni = 0, nch = 0, maxw = 0;
+  int nf = 0, ni = 0, nch = 0, maxw = 0, nfw = 0;
   for (int i = 0; i < n; ++i) {
     H[i].dd.base = base;
     base += H[i].dd.plane;
@@ -300,9 +319,12 @@ bool plan(const lbm3_domain *d, int n, const lbm3_options *o, std::vector<DomHos
     ni += H[i].dd.n_ibb;
     nch += (d[i].ny + 15) / 16;
     int mw = 0;
-    for (const TileShape &t : kTiles) mw = std::max(mw, tiles_of(d[i].nx, d[i].ny, t.tx, t.ty));
+    for (const Candidate &t : kCands)
+      if (t.kernel == MODE_TILE) mw = std::max(mw, tiles_of(d[i].nx, d[i].ny, t.tx, t.ty));
+    mw = std::max(mw, tiles_of(d[i].nx, d[i].ny, 122, kMinStripRows));
     if (o->tile_x > 0 && o->tile_y > 0) mw = std::max(mw, tiles_of(d[i].nx, d[i].ny, o->tile_x, o->tile_y));
     maxw += mw;
+    nfw += tiles_of(d[i].nx, d[i].ny, kFieldTileX, kFieldTileY);
   }
   const int prec = o->precision;
   L.total_plane = base;
@@ -310,6 +332,7 @@ bool plan(const lbm3_domain *d, int n, const lbm3_options *o, std::vector<DomHos
   L.n_ibb = ni;
   L.n_chunks = nch;
   L.max_work = maxw;
+  L.n_fwork = nfw;
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t r = off;
@@ -322,9 +345,11 @@ bool plan(const lbm3_domain *d, int n, const lbm3_options *o, std::vector<DomHos
   }
   L.off_flags = take((size_t)base);
   L.off_fill = take(sizeof(FillNode) * std::max(nf, 1));
+  L.off_fillC = take(3 * t_size(prec) * std::max(nf, 1));
   L.off_ibb = take(sizeof(IbbNode) * std::max(ni, 1));
   L.off_doms = take(sizeof(DomainDev) * n);
   L.off_work = take(sizeof(WorkItem) * maxw);
+  L.off_fwork = take(sizeof(WorkItem) * nfw);
   L.off_partial = take(sizeof(double) * 3 * nch);
   L.off_chunk_dom = take(sizeof(int) * nch);
   L.off_chunk_first = take(sizeof(int) * (n + 1));
@@ -347,9 +372,12 @@ struct lbm3_ctx {
   int cur = 0;
   long steps = 0;
   int tx = 32, ty = 8;
+  int mode = MODE_TILE;
   int persistent = 0;
   int graph_block = 0;
   std::vector<WorkItem> work;
+  std::vector<WorkItem> fwork;  // tiles of the field export
+  std::vector<int> fwork_off, fwork_n;
   hipGraphExec_t graph = nullptr;
   bool graph_valid = false;
   std::string err;
@@ -375,20 +403,39 @@ lbm3_status hip_fail(lbm3_ctx *c, hipError_t e, const char *what) {
     if (e_ != hipSuccess) return hip_fail(c, e_, #call);   \
   } while (0)
 
-void build_work(lbm3_ctx *c) {
-  c->work.clear();
+void build_work_for(lbm3_ctx *c, int mode, int tx, int ty, std::vector<WorkItem> &work,
+                    std::vector<int> *offs, std::vector<int> *counts) {
+  work.clear();
+  if (offs) offs->assign(c->n, 0);
+  if (counts) counts->assign(c->n, 0);
   for (int d = 0; d < c->n; ++d) {
     DomainDev &D = c->doms[d];
-    D.work_off = (int)c->work.size();
-    for (int y = 0; y < D.ny; y += c->ty)
-      for (int x = 0; x < D.nx; x += c->tx) c->work.push_back(WorkItem{d, x, y, 0});
-    D.n_work = (int)c->work.size() - D.work_off;
+    const int off = (int)work.size();
+    if (mode == MODE_TILE) {
+      for (int y = 0; y < D.ny; y += ty)
+        for (int x = 0; x < D.nx; x += tx)
+          work.push_back(WorkItem{d, x, y, std::min(x + tx, D.nx), std::min(y + ty, D.ny), 0, 0, 0});
+    } else {
+      const int W = (mode == MODE_STRIP128 ? 128 : 256) - 6;
+      const int ns = (D.nx + W - 1) / W;
+      const int wd = (D.nx + ns - 1) / ns;
+      for (int y = 0; y < D.ny; y += ty)
+        for (int x = 0; x < D.nx; x += wd)
+          work.push_back(WorkItem{d, x, y, std::min(x + wd, D.nx), std::min(y + ty, D.ny), 0, 0, 0});
+    }
+    if (offs) (*offs)[d] = off;
+    if (counts) (*counts)[d] = (int)work.size() - off;
   }
 }
+
+// Work list of the fused step kernel (tiles or strips).  The field export always uses the tile
+// kernel with its own tile list (built once at creation).
+void build_work(lbm3_ctx *c) { build_work_for(c, c->mode, c->tx, c->ty, c->work, nullptr, nullptr); }
 
 lbm3_status upload_tables(lbm3_ctx *c) {
   HIPC(c, hipMemcpyAsync(c->at<void>(c->L.off_doms), c->doms.data(), sizeof(DomainDev) * c->n, hipMemcpyHostToDevice, c->stream));
   HIPC(c, hipMemcpyAsync(c->at<void>(c->L.off_work), c->work.data(), sizeof(WorkItem) * c->work.size(), hipMemcpyHostToDevice, c->stream));
+  HIPC(c, hipMemcpyAsync(c->at<void>(c->L.off_fwork), c->fwork.data(), sizeof(WorkItem) * c->fwork.size(), hipMemcpyHostToDevice, c->stream));
   HIPC(c, hipStreamSynchronize(c->stream));
   return LBM3_OK;
 }
@@ -402,6 +449,8 @@ StepArgs<S, T> step_args(lbm3_ctx *c, int from) {
   a.work_end = (int)c->work.size();
   a.flags = c->at<uint8_t>(c->L.off_flags);
   a.ibb = c->at<IbbNode>(c->L.off_ibb);
+  a.fillC = c->at<T>(c->L.off_fillC);
+  a.remap = 0;
   a.fin = c->at<S>(c->L.off_F[from]);
   a.rin = c->at<T>(c->L.off_R[from]);
   a.fout = c->at<S>(c->L.off_F[1 - from]);
@@ -421,17 +470,23 @@ FillArgs<T> fill_args(lbm3_ctx *c, int which) {
   f.doms = c->at<DomainDev>(c->L.off_doms);
   f.flags = c->at<uint8_t>(c->L.off_flags);
   f.rho = c->at<T>(c->L.off_R[which]);
+  f.fillC = c->at<T>(c->L.off_fillC);
   return f;
 }
 
+// ev (optional): 3 events per step around the fill and the fused kernel.
 template <typename S, typename T>
 lbm3_status enqueue_steps_t(lbm3_ctx *c, int nsteps, hipStream_t s, hipEvent_t *ev) {
-  const int grid = c->persistent > 0 ? std::min(c->persistent, (int)c->work.size()) : (int)c->work.size();
+  const int nw = (int)c->work.size();
+  const bool persistent = c->persistent > 0;
+  const int grid = persistent ? std::min(c->persistent, nw) : round_up(nw, 8);
   for (int k = 0; k < nsteps; ++k) {
+    StepArgs<S, T> a = step_args<S, T>(c, c->cur);
+    a.remap = persistent ? 0 : 1;
     if (ev) HIPC(c, hipEventRecord(ev[3 * k], s));
     HIPC(c, launch_fill<T>(fill_args<T>(c, c->cur), s));
     if (ev) HIPC(c, hipEventRecord(ev[3 * k + 1], s));
-    HIPC(c, (launch_step<S, T>(step_args<S, T>(c, c->cur), grid, false, s)));
+    HIPC(c, (launch_step<S, T>(a, grid, c->mode, false, s)));
     if (ev) HIPC(c, hipEventRecord(ev[3 * k + 2], s));
     c->cur = 1 - c->cur;
   }
@@ -496,6 +551,20 @@ void init_state(const lbm3_domain *d, int n, const std::vector<DomHost> &H, int6
         R[3 * D.base + D.plane + li] = (T)r1;
         R[3 * D.base + 2 * D.plane + li] = (T)r2;
       }
+    // The first density slot of a fill node holds the index of its FillNode record; the filled
+    // C of each step lives in the compact fillC array.
+    for (size_t p = 0; p < H[dd].fill.size(); ++p) {
+      const int idx = D.fill_off + (int)p;
+      T v;
+      if constexpr (sizeof(T) == 4) {
+        int32_t bits = idx;
+        memcpy(&v, &bits, 4);
+      } else {
+        int64_t bits = idx;
+        memcpy(&v, &bits, 8);
+      }
+      R[3 * D.base + H[dd].fill[p].li] = v;
+    }
   }
 }
 
@@ -503,12 +572,15 @@ template <typename S, typename T>
 lbm3_status fields_t(lbm3_ctx *c, int dom, void *rho, void *u, void *force) {
   HIPC(c, launch_fill<T>(fill_args<T>(c, c->cur), c->stream));
   StepArgs<S, T> a = step_args<S, T>(c, c->cur);
-  a.work_begin = c->doms[dom].work_off;
-  a.work_end = c->doms[dom].work_off + c->doms[dom].n_work;
+  a.work = c->at<WorkItem>(c->L.off_fwork);
+  a.work_begin = c->fwork_off[dom];
+  a.work_end = c->fwork_off[dom] + c->fwork_n[dom];
+  a.tile_x = kFieldTileX;
+  a.tile_y = kFieldTileY;
   a.out_rho = reinterpret_cast<T *>(rho);
   a.out_u = reinterpret_cast<T *>(u);
   a.out_force = reinterpret_cast<T *>(force);
-  HIPC(c, (launch_step<S, T>(a, c->doms[dom].n_work, true, c->stream)));
+  HIPC(c, (launch_step<S, T>(a, c->fwork_n[dom], MODE_TILE, true, c->stream)));
   return LBM3_OK;
 }
 
@@ -565,18 +637,13 @@ lbm3_status lbm3_create(const lbm3_domain *d, int32_t n, const lbm3_options *o, 
   c->ws = reinterpret_cast<char *>(dev_workspace);
   c->graph_block = o->graph_block_steps > 0 ? round_up(o->graph_block_steps, 2) : 0;
   c->persistent = o->persistent_blocks;
-  if (o->tile_x > 0 && o->tile_y > 0) {
-    c->tx = o->tile_x;
-    c->ty = o->tile_y;
+  c->mode = o->kernel > 0 ? o->kernel : MODE_TILE;
+  if (c->mode == MODE_TILE) {
+    c->tx = o->tile_x > 0 ? o->tile_x : 32;
+    c->ty = o->tile_y > 0 ? o->tile_y : 8;
   } else {
-    c->tx = 64;
-    c->ty = o->precision == LBM3_F64 ? 4 : 8;
-  }
-  if (c->tx * c->ty < kMinTileArea || c->tx * c->ty > 4096 ||
-      step_smem_bytes(c->precision, c->tx, c->ty) > 160 * 1024) {
-    g_plan_err = "tile shape out of range (area 256..4096, LDS <= 160 KiB)";
-    delete c;
-    return LBM3_EINVAL;
+    c->tx = 0;
+    c->ty = o->tile_y > 0 ? o->tile_y : 64;
   }
   for (auto &h : H) c->doms.push_back(h.dd);
   auto bail = [&](lbm3_status s) {
@@ -590,6 +657,7 @@ lbm3_status lbm3_create(const lbm3_domain *d, int32_t n, const lbm3_options *o, 
   e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
   if (e != hipSuccess) return bail(hip_fail(c, e, "hipStreamCreateWithFlags"));
   build_work(c);
+  build_work_for(c, MODE_TILE, kFieldTileX, kFieldTileY, c->fwork, &c->fwork_off, &c->fwork_n);
   // chunk tables of the mass reduction
   std::vector<int> chunk_dom, chunk_first;
   for (int i = 0; i < n; ++i) {
@@ -615,12 +683,10 @@ lbm3_status lbm3_create(const lbm3_domain *d, int32_t n, const lbm3_options *o, 
     hipError_t e2 = (call);                                   \
     if (e2 != hipSuccess) return bail(hip_fail(c, e2, #call)); \
   } while (0)
-  for (int b = 0; b < 2; ++b) {
-    CK(hipMemsetAsync(c->at<void>(L.off_F[b]), 0, Fh.size(), s));
-    CK(hipMemsetAsync(c->at<void>(L.off_R[b]), 0, Rh.size(), s));
+  for (int b = 0; b < 2; ++b) {  // both buffers: solid slots are never written by the step
+    CK(hipMemcpyAsync(c->at<void>(L.off_F[b]), Fh.data(), Fh.size(), hipMemcpyHostToDevice, s));
+    CK(hipMemcpyAsync(c->at<void>(L.off_R[b]), Rh.data(), Rh.size(), hipMemcpyHostToDevice, s));
   }
-  CK(hipMemcpyAsync(c->at<void>(L.off_F[0]), Fh.data(), Fh.size(), hipMemcpyHostToDevice, s));
-  CK(hipMemcpyAsync(c->at<void>(L.off_R[0]), Rh.data(), Rh.size(), hipMemcpyHostToDevice, s));
   CK(hipMemcpyAsync(c->at<void>(L.off_flags), flags.data(), flags.size(), hipMemcpyHostToDevice, s));
   if (!fill.empty()) CK(hipMemcpyAsync(c->at<void>(L.off_fill), fill.data(), sizeof(FillNode) * fill.size(), hipMemcpyHostToDevice, s));
   if (!ibb.empty()) CK(hipMemcpyAsync(c->at<void>(L.off_ibb), ibb.data(), sizeof(IbbNode) * ibb.size(), hipMemcpyHostToDevice, s));
@@ -659,13 +725,6 @@ lbm3_status lbm3_step(lbm3_ctx *c, int32_t nsteps) {
   lbm3_status st = enqueue_steps(c, left, c->stream);
   if (st != LBM3_OK) return st;
   c->steps += nsteps;
-  return LBM3_OK;
-}
-
-lbm3_status lbm3_fill(lbm3_ctx *c) {
-  if (!c) return LBM3_EINVAL;
-  if (c->precision == LBM3_F64) HIPC(c, launch_fill<double>(fill_args<double>(c, c->cur), c->stream));
-  else HIPC(c, launch_fill<float>(fill_args<float>(c, c->cur), c->stream));
   return LBM3_OK;
 }
 
@@ -740,7 +799,7 @@ lbm3_status lbm3_set_state(lbm3_ctx *c, const void *dev_src) {
 }
 
 lbm3_status lbm3_kernel_times(lbm3_ctx *c, int32_t nsteps, double *ms_fill, double *ms_step) {
-  if (!c || nsteps < 1 || !ms_fill || !ms_step) return LBM3_EINVAL;
+  if (!c || nsteps < 1 || !ms_step || !ms_fill) return LBM3_EINVAL;
   std::vector<hipEvent_t> ev(3 * nsteps, nullptr);
   for (auto &e : ev) HIPC(c, hipEventCreate(&e));
   lbm3_status st = enqueue_steps(c, nsteps, c->stream, ev.data());
@@ -763,38 +822,41 @@ lbm3_status lbm3_kernel_times(lbm3_ctx *c, int32_t nsteps, double *ms_fill, doub
   return st;
 }
 
-lbm3_status lbm3_autotune(lbm3_ctx *c, int32_t steps_per_candidate, int32_t *tile_xy) {
+lbm3_status lbm3_autotune(lbm3_ctx *c, int32_t steps_per_candidate, int32_t *choice) {
   if (!c || steps_per_candidate < 1) return LBM3_EINVAL;
-  const int otx = c->tx, oty = c->ty;
   double best = 1e300;
-  int btx = otx, bty = oty;
-  for (const TileShape &t : kTiles) {
-    if (t.tx * t.ty < kMinTileArea || step_smem_bytes(c->precision, t.tx, t.ty) > 160 * 1024) continue;
+  Candidate bc{c->mode, c->tx, c->ty};
+  for (const Candidate &t : kCands) {
+    if (t.kernel == MODE_TILE && step_smem_bytes(c->precision, MODE_TILE, t.tx, t.ty) > 160 * 1024) continue;
+    if (t.kernel != MODE_TILE && step_smem_bytes(c->precision, t.kernel, 0, 0) > 160 * 1024) continue;
+    c->mode = t.kernel;
     c->tx = t.tx;
     c->ty = t.ty;
     build_work(c);
     lbm3_status st = upload_tables(c);
     if (st != LBM3_OK) return st;
-    double mf, ms;
-    enqueue_steps(c, 2, c->stream);  // warm-up
+    st = enqueue_steps(c, 2, c->stream);  // warm-up
+    if (st != LBM3_OK) return st;
     c->steps += 2;
+    double mf, ms;
     st = lbm3_kernel_times(c, steps_per_candidate, &mf, &ms);
     if (st != LBM3_OK) return st;
     if (ms < best) {
       best = ms;
-      btx = t.tx;
-      bty = t.ty;
+      bc = t;
     }
   }
-  c->tx = btx;
-  c->ty = bty;
+  c->mode = bc.kernel;
+  c->tx = bc.tx;
+  c->ty = bc.ty;
   build_work(c);
   c->graph_valid = false;
   lbm3_status st = upload_tables(c);
   if (st != LBM3_OK) return st;
-  if (tile_xy) {
-    tile_xy[0] = btx;
-    tile_xy[1] = bty;
+  if (choice) {
+    choice[0] = bc.kernel;
+    choice[1] = bc.tx;
+    choice[2] = bc.ty;
   }
   return LBM3_OK;
 }
@@ -812,6 +874,7 @@ lbm3_status lbm3_query(const lbm3_ctx *c, int32_t key, double *value) {
     case 5: *value = c->ty; break;
     case 6: *value = (double)c->work.size(); break;
     case 7: *value = (double)c->steps; break;
+    case 8: *value = c->mode; break;
     default: return LBM3_EINVAL;
   }
   return LBM3_OK;

@@ -48,10 +48,16 @@ struct DomainDev {
   double g[2];     // body acceleration
 };
 
-// A solid node whose C is filled (C_SB or C_SB2), with its fluid-pointing unit normal.
+// A solid node whose C is filled (C_SB or C_SB2), with its fluid-pointing unit normal and the
+// point D0 where its normal line first meets the fluid (two plane indices and a weight; the
+// normal is fixed, so D0 is found once at set-up).
 struct FillNode {
   int32_t dom, i, j, li;  // domain, coordinates, index within the domain's plane
+  int32_t d0a, d0b;       // plane indices of the interpolation nodes of D0
+  double d0w;             // C(D0) = C(d0a) + d0w (C(d0b) - C(d0a))
   double nx, ny;
+  uint64_t mask;          // fluid indicator of the 7 x 7 block around the node:
+                          // bit (dy+3)*7 + (dx+3) for offsets -3..3
 };
 
 // A fluid node with interpolated-bounce-back links: q[a-1] for direction a = 1..8 is the
@@ -62,8 +68,9 @@ struct IbbNode {
   double q[8];
 };
 
+// A tile (x0, y0 and the context's tile shape) or a strip (columns x0..x1-1, rows y0..y1-1).
 struct WorkItem {
-  int32_t dom, x0, y0, pad_;
+  int32_t dom, x0, y0, x1, y1, pad0_, pad1_, pad2_;
 };
 
 __host__ __device__ inline int64_t plane_index(int i, int j, int pitch) {
@@ -96,10 +103,11 @@ __host__ __device__ inline LineHit march_line(int pi, int pj, double dx, double 
   const int sx = dx > kEpsDir ? 1 : (dx < -kEpsDir ? -1 : 0);
   const int sy = dy > kEpsDir ? 1 : (dy < -kEpsDir ? -1 : 0);
   const double ax = dx < 0 ? -dx : dx, ay = dy < 0 ? -dy : dy;
+  const double iax = sx ? 1.0 / ax : 0.0, iay = sy ? 1.0 / ay : 0.0;
   int kx = 1, ky = 1;
   for (int guard = 0; guard < 256; ++guard) {
-    const double tx = sx ? (double)kx / ax : 1e300;
-    const double ty = sy ? (double)ky / ay : 1e300;
+    const double tx = sx ? (double)kx * iax : 1e300;  // t of the next vertical line
+    const double ty = sy ? (double)ky * iay : 1e300;  // t of the next horizontal line
     const double t = tx < ty ? tx : ty;
     if (t > kTMax) return h;
     if (tx <= ty) {

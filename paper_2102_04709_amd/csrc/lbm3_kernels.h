@@ -15,7 +15,8 @@ struct FillArgs {
   int n_fill;
   const DomainDev *doms;
   const uint8_t *flags;
-  T *rho;  // density planes of the current state (read at fluid nodes, written at fill nodes)
+  const T *rho;  // density planes of the current state
+  T *fillC;      // [3 * n_fill] filled C of this step
 };
 
 template <typename S, typename T>
@@ -25,6 +26,8 @@ struct StepArgs {
   int work_begin, work_end;
   const uint8_t *flags;
   const IbbNode *ibb;
+  const T *fillC;  // [3 * n_fill] filled C of this step, indexed from the fill nodes' first slot
+  int remap;  // 1: XCD-aware mapping, one work item per work-group
   const S *fin;
   const T *rin;
   S *fout;
@@ -46,13 +49,15 @@ struct MassArgs {
   int *bad;
 };
 
+enum { MODE_TILE = 0, MODE_STRIP128 = 1, MODE_STRIP256 = 2 };
+
 template <typename T>
 hipError_t launch_fill(const FillArgs<T> &a, hipStream_t s);
 template <typename S, typename T>
-hipError_t launch_step(const StepArgs<S, T> &a, int grid, bool fields, hipStream_t s);
+hipError_t launch_step(const StepArgs<S, T> &a, int grid, int mode, bool fields, hipStream_t s);
 template <typename T>
 hipError_t launch_mass(const MassArgs<T> &a, int n_chunks, int n_dom, double *out, hipStream_t s);
-size_t step_smem_bytes(int precision, int tx, int ty);
+size_t step_smem_bytes(int precision, int mode, int tx, int ty);
 hipError_t init_kernel_attributes();
 
 }  // namespace lbm3

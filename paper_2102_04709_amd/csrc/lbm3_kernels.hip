@@ -57,102 +57,384 @@ __device__ __forceinline__ void store_s(S *p, T v) {
 template <>
 __device__ __forceinline__ void store_s<__half, float>(__half *p, float v) { *p = __float2half_rn(v); }
 
-__device__ __forceinline__ int wrapi(int v, int n) {
-  int r = v % n;
-  return r < 0 ? r + n : r;
+__device__ __forceinline__ int wrap_small(int v, int n) {
+  while (v < 0) v += n;
+  while (v >= n) v -= n;
+  return v;
 }
 
 // Index of node (gx, gy) within the domain's plane: periodic axes wrap, the Zou-He x axis
 // clamps to the boundary columns (zero-gradient ghost columns), a non-periodic y axis clamps to
 // the two off-grid solid rows.
 __device__ __forceinline__ int64_t node_index(int gx, int gy, const DomainDev &D) {
-  gx = D.bcx == BCX_ZOUHE ? min(max(gx, 0), D.nx - 1) : wrapi(gx, D.nx);
-  gy = D.yper ? wrapi(gy, D.ny) : min(max(gy, -2), D.ny + 1);
+  gx = D.bcx == BCX_ZOUHE ? min(max(gx, 0), D.nx - 1) : wrap_small(gx, D.nx);
+  gy = D.yper ? wrap_small(gy, D.ny) : min(max(gy, -2), D.ny + 1);
   return plane_index(gx, gy, D.pitch);
 }
 
 // ------------------------------------------------------------------------------------------
-// Wetting fill, Eq. (19)-(22).
+// Wetting fill, Eq. (19)-(22), of one solid boundary node, computed where it is needed: the
+// fused kernels call it for every fill node in the halo they load, so the filled C never goes
+// through HBM.  All geometry is FP64; C at fluid nodes is rho_k / rho of the stored densities.
+// The march tests fluid nodes with the node's 7 x 7 fluid mask and reads the flag plane only
+// beyond it.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void wet_fill(FillArgs<T> A) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= A.n_fill) return;
-  const FillNode fn = A.fill[idx];
-  const DomainDev &D = A.doms[fn.dom];
-  const uint8_t *flags = A.flags + D.base;
-  const T *r0 = A.rho + 3 * D.base, *r1 = r0 + D.plane, *r2 = r1 + D.plane;
+__device__ __forceinline__ double cfrac_at(const T *r, int64_t P, int64_t q, int k) {
+  const double a = (double)r[q], b = (double)r[P + q], d = (double)r[2 * P + q];
+  const double v = k == 0 ? a : (k == 1 ? b : d);
+  return v / (a + b + d);
+}
+
+// Lane `line` (0..3) of the four lanes that fill one node: fluid k = line / 2, side
+// s = line % 2.  Every lane forms C at D0 and the angle of its fluid, marches its line and
+// interpolates; the lanes of a fluid then combine their values with Eq. (22) and lane 0
+// receives the second fluid's value.  Returns (C1, C2) in lane 0.
+template <typename T>
+__device__ __forceinline__ void fill_lanes(const FillNode &fn, const DomainDev &D, const uint8_t *flags,
+                                           const T *r, int line, bool active, double &c1, double &c2) {
+  const int64_t P = D.plane;
   auto fluid_at = [&](int i, int j) -> bool {
+    const int dx = i - fn.i, dy = j - fn.j;
+    if (dx >= -3 && dx <= 3 && dy >= -3 && dy <= 3) return (fn.mask >> ((dy + 3) * 7 + dx + 3)) & 1;
     if (D.bcx == BCX_ZOUHE) {
       if (i < 0 || i >= D.nx) return false;
     } else {
-      i = wrapi(i, D.nx);
+      i = wrap_small(i, D.nx);
     }
-    if (D.yper) j = wrapi(j, D.ny);
+    if (D.yper) j = wrap_small(j, D.ny);
     else if (j < 0 || j >= D.ny) return false;
     return (flags[plane_index(i, j, D.pitch)] & FL_SOLID) == 0;
   };
-  auto cval = [&](int i, int j, double *c) {
-    if (D.bcx != BCX_ZOUHE) i = wrapi(i, D.nx);
-    if (D.yper) j = wrapi(j, D.ny);
-    const int64_t q = plane_index(i, j, D.pitch);
-    const double a = (double)r0[q], b = (double)r1[q], d = (double)r2[q];
-    const double s = a + b + d;
-    c[0] = a / s;
-    c[1] = b / s;
-    c[2] = d / s;
-  };
-  auto interp = [&](const LineHit &h, double *c) {
-    double c0[3], c1[3];
-    cval(h.i0, h.j0, c0);
-    cval(h.i1, h.j1, c1);
-    for (int k = 0; k < 3; ++k) c[k] = c0[k] + h.w * (c1[k] - c0[k]);
+  auto node_q = [&](int i, int j) -> int64_t {
+    if (D.bcx != BCX_ZOUHE) i = wrap_small(i, D.nx);
+    if (D.yper) j = wrap_small(j, D.ny);
+    return plane_index(i, j, D.pitch);
   };
   const double PI = 3.14159265358979323846;
-  const double nx = fn.nx, ny = fn.ny, tx = -ny, ty = nx;
-  // C used in the weighted contact angle (Eq. 21): the value where the normal line meets the
-  // fluid (the set-up guarantees that it does).
+  const int k = line >> 1;
+  // C at D0 for the weighted contact angle of Eq. (21).
   double Cb[3];
-  interp(march_line(fn.i, fn.j, nx, ny, fluid_at), Cb);
-  double th[2];
-  {
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const double ca = cfrac_at(r, P, fn.d0a, q), cb = cfrac_at(r, P, fn.d0b, q);
+    Cb[q] = ca + fn.d0w * (cb - ca);
+  }
+  double th;
+  if (k == 0) {
     const double a = fmax(Cb[1], 0.0), b = fmax(Cb[2], 0.0), den = a + b;
-    th[0] = den > 1e-12 ? (b * D.th13 + a * D.th12) / den : 0.5 * (D.th13 + D.th12);
-    const double a2 = fmax(Cb[0], 0.0), den2 = a2 + b;
+    th = den > 1e-12 ? (b * D.th13 + a * D.th12) / den : 0.5 * (D.th13 + D.th12);
+  } else {
+    const double a2 = fmax(Cb[0], 0.0), b = fmax(Cb[2], 0.0), den2 = a2 + b;
     const double th21 = PI - D.th12;
-    th[1] = den2 > 1e-12 ? (b * D.th23 + a2 * th21) / den2 : 0.5 * (D.th23 + th21);
+    th = den2 > 1e-12 ? (b * D.th23 + a2 * th21) / den2 : 0.5 * (D.th23 + th21);
   }
-  double CP[3];
-  for (int k = 0; k < 2; ++k) {
-    const double tk = fmin(fmax(th[k], 5.0 * PI / 180.0), 175.0 * PI / 180.0);
-    const double phi = fabs(0.5 * PI - tk);
-    const double c = cos(phi), s = sin(phi);
-    const LineHit l1 = march_line(fn.i, fn.j, c * nx + s * tx, c * ny + s * ty, fluid_at);
-    const LineHit l2 = march_line(fn.i, fn.j, c * nx - s * tx, c * ny - s * ty, fluid_at);
-    double v;
-    if (l1.ok && l2.ok) {
-      double v1[3], v2[3];
-      interp(l1, v1);
-      interp(l2, v2);
-      v = tk <= 0.5 * PI ? fmax(v1[k], v2[k]) : fmin(v1[k], v2[k]);  // Eq. (22)
-    } else if (l1.ok || l2.ok) {
-      double v1[3];
-      interp(l1.ok ? l1 : l2, v1);
-      v = v1[k];
-    } else {
-      v = Cb[k];
+  const double tk = fmin(fmax(th, 5.0 * PI / 180.0), 175.0 * PI / 180.0);
+  const double phi = fabs(0.5 * PI - tk);
+  double sp, cp;
+  sincos(phi, &sp, &cp);
+  if (line & 1) sp = -sp;
+  const double nx = fn.nx, ny = fn.ny, tx = -ny, ty = nx;
+  double v = 0.0;
+  int ok = 0;
+  if (active) {
+    const LineHit h = march_line(fn.i, fn.j, cp * nx + sp * tx, cp * ny + sp * ty, fluid_at);
+    if (h.ok) {
+      const double ca = cfrac_at(r, P, node_q(h.i0, h.j0), k), cb = cfrac_at(r, P, node_q(h.i1, h.j1), k);
+      v = ca + h.w * (cb - ca);
+      ok = 1;
     }
-    CP[k] = v;
   }
-  CP[2] = 1.0 - CP[0] - CP[1];
-  const int64_t q = fn.li;
-  T *w0 = A.rho + 3 * D.base;
-  w0[q] = (T)CP[0];
-  w0[D.plane + q] = (T)CP[1];
-  w0[2 * D.plane + q] = (T)CP[2];
+  const double vo = __shfl_xor(v, 1);
+  const int oko = __shfl_xor(ok, 1);
+  double c;
+  if (ok && oko) c = tk <= 0.5 * PI ? fmax(v, vo) : fmin(v, vo);  // Eq. (22)
+  else if (ok) c = v;
+  else if (oko) c = vo;
+  else c = Cb[k];
+  c1 = c;
+  c2 = __shfl_xor(c, 2);
+}
+
+// Index of the fill node whose data a solid fill node's first density slot holds.
+__device__ __forceinline__ int fill_index(float v) { return __float_as_int(v); }
+__device__ __forceinline__ int fill_index(double v) { return (int)__double_as_longlong(v); }
+
+// Wetting-fill kernel: one thread per fill node; the three filled C's go to the compact array
+// fillC[3 * node] that the fused kernels read (so the solid slots of the state stay constant).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void wet_fill(FillArgs<T> A) {
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int idx = gid >> 2, line = gid & 3;
+  const bool active = idx < A.n_fill;
+  const FillNode fn = A.fill[active ? idx : 0];
+  const DomainDev &D = A.doms[fn.dom];
+  double c1, c2;
+  fill_lanes<T>(fn, D, A.flags + D.base, A.rho + 3 * D.base, line, active, c1, c2);
+  if (active && line == 0) {
+    A.fillC[3 * idx] = (T)c1;
+    A.fillC[3 * idx + 1] = (T)c2;
+    A.fillC[3 * idx + 2] = (T)(1.0 - c1 - c2);
+  }
+}
+
+// C and rho of a loaded node for the colour-gradient stencil: fluid nodes give rho_k / rho;
+// fill nodes the filled C of this step (rho := 1); other solid nodes zero (rho := 1).
+template <typename T>
+__device__ __forceinline__ void node_composition(uint8_t fl, T a, T b, T c, const T *fillC, T out[4]) {
+  if (fl & FL_SOLID) {
+    if (fl & FL_FILL) {
+      const T *v = fillC + 3 * fill_index(a);
+      out[0] = v[0]; out[1] = v[1]; out[2] = v[2];
+    } else {
+      out[0] = out[1] = out[2] = T(0);
+    }
+    out[3] = T(1);
+  } else {
+    const T r = a + b + c;
+    out[0] = a / r; out[1] = b / r; out[2] = c / r; out[3] = r;
+  }
 }
 
 // ------------------------------------------------------------------------------------------
-// Fused step.
+// Per-node pieces of the fused step, shared by the tile and the strip kernels.  Neighbour
+// values are passed in D2Q9 order c[a] = psi(x + e_a).
+
+// Eq. (12): (1/c_s^2) sum_a w_a psi(x + e_a) e_a.
+template <typename T>
+__device__ __forceinline__ void grad9(const T *c, T &gx, T &gy) {
+  gx = T(1.0 / 3.0) * (c[1] - c[3]) + T(1.0 / 12.0) * (c[5] - c[6] - c[7] + c[8]);
+  gy = T(1.0 / 3.0) * (c[2] - c[4]) + T(1.0 / 12.0) * (c[5] + c[6] - c[7] - c[8]);
+}
+
+// Eq. (10) stress sum over the fluid pairs 12, 13, 23 (the double sum over ordered pairs with
+// the factor 1/2 equals the sum over unordered pairs, since G_lk = -G_kl), and the pair normals
+// n_kl = G_kl / |G_kl| (zero when |G_kl| <= eps).
+template <typename T>
+__device__ __forceinline__ void pair_stress(const T cc[3], const T g[3][2], T rho, const DomainDev &D,
+                                            T eps, T &txx, T &txy, T &tyy, T nrm[6]) {
+  txx = txy = tyy = T(0);
+  const int pk[3] = {0, 0, 1}, pl[3] = {1, 2, 2};
+#pragma unroll
+  for (int pr = 0; pr < 3; ++pr) {
+    const int k = pk[pr], l = pl[pr];
+    const T Gx = cc[l] * g[k][0] - cc[k] * g[l][0];
+    const T Gy = cc[l] * g[k][1] - cc[k] * g[l][1];
+    const T mag = sqrt(Gx * Gx + Gy * Gy);
+    const T rk = cc[k] * rho, rl = cc[l] * rho;
+    const T Akl = fmin(fmax(T(1e6) * rk * rl, T(0)), T(1));
+    if (mag > eps) {
+      const T nx = Gx / mag, ny = Gy / mag;
+      const T coef = (T)D.sig[pr] * Akl * mag;
+      txx += coef * (T(1) - nx * nx);
+      txy += coef * (-nx * ny);
+      tyy += coef * (T(1) - ny * ny);
+      nrm[2 * pr] = nx;
+      nrm[2 * pr + 1] = ny;
+    } else {
+      nrm[2 * pr] = T(0);
+      nrm[2 * pr + 1] = T(0);
+    }
+  }
+}
+
+// F_s = div T with Eq. (12) on the stress components.
+template <typename T>
+__device__ __forceinline__ void div_stress(const T *xx, const T *xy, const T *yy, T &Fx, T &Fy) {
+  Fx = T(1.0 / 3.0) * (xx[1] - xx[3]) + T(1.0 / 3.0) * (xy[2] - xy[4]) +
+       T(1.0 / 12.0) * (xx[5] - xx[6] - xx[7] + xx[8] + xy[5] + xy[6] - xy[7] - xy[8]);
+  Fy = T(1.0 / 3.0) * (xy[1] - xy[3]) + T(1.0 / 3.0) * (yy[2] - yy[4]) +
+       T(1.0 / 12.0) * (xy[5] - xy[6] - xy[7] + xy[8] + yy[5] + yy[6] - yy[7] - yy[8]);
+}
+
+// Eq. (1)-(9), (11) on the shifted distribution f - w: MRT collision with the forcing term at
+// the mixture relaxation time of Eq. (7).  Fx, Fy enter as the interfacial force and leave as
+// the total force (the body acceleration times rho added).
+template <typename T>
+__device__ __forceinline__ void collide_shifted(const T f[9], T &Fx, T &Fy, T r0, T r1, T r2,
+                                                const DomainDev &D, T fd[9], T &ux, T &uy) {
+  const T s14 = f[1] + f[2] + f[3] + f[4], s58 = f[5] + f[6] + f[7] + f[8];
+  const T drho = f[0] + s14 + s58;
+  const T m1 = -T(4) * f[0] - s14 + T(2) * s58;
+  const T m2 = T(4) * f[0] - T(2) * s14 + s58;
+  const T jx = f[1] - f[3] + f[5] - f[6] - f[7] + f[8];
+  const T m4 = -T(2) * f[1] + T(2) * f[3] + f[5] - f[6] - f[7] + f[8];
+  const T jy = f[2] - f[4] + f[5] + f[6] - f[7] - f[8];
+  const T m6 = -T(2) * f[2] + T(2) * f[4] + f[5] + f[6] - f[7] - f[8];
+  const T m7 = f[1] - f[2] + f[3] - f[4];
+  const T m8 = f[5] - f[6] + f[7] - f[8];
+  const T rho = T(1) + drho;
+  Fx += rho * (T)D.g[0];
+  Fy += rho * (T)D.g[1];
+  const T irho = T(1) / rho;
+  ux = (jx + T(0.5) * Fx) * irho;
+  uy = (jy + T(0.5) * Fy) * irho;
+  const T tau = T(0.5) + T(3) / (r0 / (T)D.nu[0] + r1 / (T)D.nu[1] + r2 / (T)D.nu[2]);
+  const T s1 = T(1) / tau;
+  const T s4 = T(8) * (T(2) - s1) / (T(8) - s1);
+  const T ruu = rho * (ux * ux + uy * uy);
+  const T uF = ux * Fx + uy * Fy;
+  const T h1 = T(1) - T(0.5) * s1, h4 = T(1) - T(0.5) * s4;
+  // Delta_i = S_i (m_i - meq_i) - (1 - S_i/2) mF_i, scaled by diag(M M^T)^-1
+  const T d1 = (s1 * (m1 - (-T(2) * drho + T(3) * ruu)) - h1 * T(6) * uF) * T(1.0 / 36.0);
+  const T d2 = (s1 * (m2 - (drho - T(3) * ruu)) + h1 * T(6) * uF) * T(1.0 / 36.0);
+  const T d3 = -Fx * T(1.0 / 6.0);
+  const T d4 = (s4 * (m4 + rho * ux) + h4 * Fx) * T(1.0 / 12.0);
+  const T d5 = -Fy * T(1.0 / 6.0);
+  const T d6 = (s4 * (m6 + rho * uy) + h4 * Fy) * T(1.0 / 12.0);
+  const T d7 = (s1 * (m7 - rho * (ux * ux - uy * uy)) - h1 * T(2) * (ux * Fx - uy * Fy)) * T(0.25);
+  const T d8 = (s1 * (m8 - rho * ux * uy) - h1 * (ux * Fy + uy * Fx)) * T(0.25);
+  // f' = f - M^T d
+  fd[0] = f[0] - (-T(4) * d1 + T(4) * d2);
+  fd[1] = f[1] - (-d1 - T(2) * d2 + d3 - T(2) * d4 + d7);
+  fd[2] = f[2] - (-d1 - T(2) * d2 + d5 - T(2) * d6 - d7);
+  fd[3] = f[3] - (-d1 - T(2) * d2 - d3 + T(2) * d4 + d7);
+  fd[4] = f[4] - (-d1 - T(2) * d2 - d5 + T(2) * d6 - d7);
+  fd[5] = f[5] - (T(2) * d1 + d2 + d3 + d4 + d5 + d6 + d8);
+  fd[6] = f[6] - (T(2) * d1 + d2 - d3 - d4 + d5 + d6 - d8);
+  fd[7] = f[7] - (T(2) * d1 + d2 - d3 - d4 - d5 - d6 + d8);
+  fd[8] = f[8] - (T(2) * d1 + d2 + d3 + d4 - d5 - d6 - d8);
+}
+
+// Eq. (13)-(15): R_k = sum_{l != k} beta_kl (rho_k rho_l / rho) n_kl for k = 1, 2
+// (R_3 = -R_1 - R_2); out = (R_1x, R_1y, R_2x, R_2y).
+template <typename T>
+__device__ __forceinline__ void recolour_R(T r0, T r1, T r2, T rt, const T nrm[6], const DomainDev &D, T out[4]) {
+  const T irt = T(1) / rt;
+  T r3 = T(35) * r0 * r1 * r2 * irt * irt * irt;
+  r3 = fmin(fmax(r3, T(0)), T(1));
+  const T b0 = (T)D.beta0;
+  const T b12 = b0 + b0 * r3 * (T)D.gX[0];
+  const T b13 = b0 + b0 * r3 * (T)D.gX[1];
+  const T b23 = b0 + b0 * r3 * (T)D.gX[2];
+  const T a12 = b12 * r0 * r1 * irt, a13 = b13 * r0 * r2 * irt, a23 = b23 * r1 * r2 * irt;
+  out[0] = a12 * nrm[0] + a13 * nrm[2];
+  out[1] = a12 * nrm[1] + a13 * nrm[3];
+  out[2] = -a12 * nrm[0] + a23 * nrm[4];
+  out[3] = -a12 * nrm[1] + a23 * nrm[5];
+}
+
+__device__ __forceinline__ const IbbNode *find_ibb(const IbbNode *ibb, const DomainDev &D, int64_t li) {
+  int lo = D.ibb_off, hi = D.ibb_off + D.n_ibb - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (ibb[mid].li < li) lo = mid + 1;
+    else hi = mid;
+  }
+  return &ibb[lo];
+}
+
+// Recoloured populations f''_{dir,k} of Eq. (13) at a node (through the accessor): C_k (f'+w)
+// + w R_k.e_dir.
+template <typename T, class Acc>
+__device__ __forceinline__ void fluid_parts(const Acc &acc, int dx, int dy, int dir, T out[3]) {
+  const T w = wgt<T>(dir);
+  const int ex = lat_ex(dir), ey = lat_ey(dir);
+  const T fv = acc.f(dir, dx, dy) + w;
+  const T R1 = acc.R(0, dx, dy) * ex + acc.R(1, dx, dy) * ey;
+  const T R2 = acc.R(2, dx, dy) * ex + acc.R(3, dx, dy) * ey;
+  out[0] = acc.C(0, dx, dy) * fv + w * R1;
+  out[1] = acc.C(1, dx, dy) * fv + w * R2;
+  out[2] = acc.C(2, dx, dy) * fv + w * (-(R1 + R2));
+}
+
+// Eq. (16) pull-streaming into one fluid node (gx, gy) from the post-collision data around it,
+// with halfway / interpolated bounce-back, the fluid-1/3 exchanging periodic x boundary and the
+// Zou-He columns.  Produces the shifted total distribution and the three partial densities.
+template <typename T, class Acc>
+__device__ __forceinline__ void stream_node(const Acc &acc, int gx, uint8_t fl, int64_t li, const DomainDev &D,
+                                            const IbbNode *ibb, T fo[9], T &ra, T &rb, T &rc) {
+  ra = rb = rc = T(0);
+  const IbbNode *ib = ((fl & FL_CURVED) && D.n_ibb > 0) ? find_ibb(ibb, D, li) : nullptr;
+#pragma unroll
+  for (int a = 0; a < 9; ++a) {
+    const int ex = lat_ex(a), ey = lat_ey(a);
+    const int sx = gx - ex;
+    if (D.bcx == BCX_ZOUHE && (sx < 0 || sx >= D.nx)) {  // set by the Zou-He rule below
+      fo[a] = T(0);
+      continue;
+    }
+    if (!acc.solid(-ex, -ey)) {
+      T c[3];
+      fluid_parts<T>(acc, -ex, -ey, a, c);
+      fo[a] = acc.f(a, -ex, -ey);
+      const bool crossed = D.bcx == BCX_SWAP13 && (sx < 0 || sx >= D.nx);
+      if (crossed) { ra += c[2]; rb += c[1]; rc += c[0]; }
+      else { ra += c[0]; rb += c[1]; rc += c[2]; }
+    } else {
+      // the link x -> x - e_a ends in a solid node: bounce-back of the populations leaving x
+      // along -e_a (direction ab)
+      const int ab = lat_opp(a);
+      const T qd = ib ? (T)ib->q[a - 1] : T(0.5);
+      const T fab = acc.f(ab, 0, 0);
+      T own_ab[3];
+      fluid_parts<T>(acc, 0, 0, ab, own_ab);
+      if (qd < T(0.5) && !acc.solid(ex, ey)) {
+        T nb_ab[3];
+        fluid_parts<T>(acc, ex, ey, ab, nb_ab);
+        const T c1 = T(2) * qd, c2 = T(1) - T(2) * qd;
+        fo[a] = c1 * fab + c2 * acc.f(ab, ex, ey);
+        ra += c1 * own_ab[0] + c2 * nb_ab[0];
+        rb += c1 * own_ab[1] + c2 * nb_ab[1];
+        rc += c1 * own_ab[2] + c2 * nb_ab[2];
+      } else if (qd < T(0.5)) {
+        fo[a] = fab;
+        ra += own_ab[0]; rb += own_ab[1]; rc += own_ab[2];
+      } else {
+        T own_a[3];
+        fluid_parts<T>(acc, 0, 0, a, own_a);
+        const T c1 = T(1) / (T(2) * qd), c2 = T(1) - c1;
+        fo[a] = c1 * fab + c2 * acc.f(a, 0, 0);
+        ra += c1 * own_ab[0] + c2 * own_a[0];
+        rb += c1 * own_ab[1] + c2 * own_a[1];
+        rc += c1 * own_ab[2] + c2 * own_a[2];
+      }
+    }
+  }
+  if (D.bcx == BCX_ZOUHE && (gx == 0 || gx == D.nx - 1)) {
+    // Zou-He non-equilibrium bounce-back on the total distribution (unshifted).
+    T ft[9];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) ft[a] = fo[a] + wgt<T>(a);
+    if (gx == 0) {
+      const T u = (T)D.u_in;
+      const T rw = (ft[0] + ft[2] + ft[4] + T(2) * (ft[3] + ft[6] + ft[7])) / (T(1) - u);
+      ft[1] = ft[3] + T(2.0 / 3.0) * rw * u;
+      ft[5] = ft[7] - T(0.5) * (ft[2] - ft[4]) + rw * u / T(6);
+      ft[8] = ft[6] + T(0.5) * (ft[2] - ft[4]) + rw * u / T(6);
+      rc += ft[1] + ft[5] + ft[8];  // incoming populations carry pure fluid 3
+      fo[1] = ft[1] - wgt<T>(1);
+      fo[5] = ft[5] - wgt<T>(5);
+      fo[8] = ft[8] - wgt<T>(8);
+    } else {
+      const T ro = (T)D.rho_out;
+      const T ux = -T(1) + (ft[0] + ft[2] + ft[4] + T(2) * (ft[1] + ft[5] + ft[8])) / ro;
+      ft[3] = ft[1] - T(2.0 / 3.0) * ro * ux;
+      ft[7] = ft[5] + T(0.5) * (ft[2] - ft[4]) - ro * ux / T(6);
+      ft[6] = ft[8] - T(0.5) * (ft[2] - ft[4]) - ro * ux / T(6);
+      // unknown populations carry the node's own composition
+      const T C0 = acc.C(0, 0, 0), C1 = acc.C(1, 0, 0), C2 = acc.C(2, 0, 0);
+      ra += C0 * ft[3]; rb += C1 * ft[3]; rc += C2 * ft[3];
+      ra += C0 * ft[6]; rb += C1 * ft[6]; rc += C2 * ft[6];
+      ra += C0 * ft[7]; rb += C1 * ft[7]; rc += C2 * ft[7];
+      fo[3] = ft[3] - wgt<T>(3);
+      fo[6] = ft[6] - wgt<T>(6);
+      fo[7] = ft[7] - wgt<T>(7);
+    }
+  }
+}
+
+// Work item of this work-group.  With remap, consecutive items go to the same XCD (gfx950
+// dispatches work-group b to XCD b % 8), so neighbouring tiles share an L2 and their halo
+// rows are fetched from HBM once; the grid is then a multiple of 8 with one item per group.
+__device__ __forceinline__ int first_item(int remap) {
+  if (!remap) return blockIdx.x;
+  const int per = gridDim.x >> 3;
+  return (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+}
+
+// ------------------------------------------------------------------------------------------
+// Tile kernel: one work-group per (domain, TX x TY tile); C on tile+3 rings, stress on tile+2,
+// collision on tile+1, all in LDS.  Also provides the field export (FIELDS = true).
 template <typename T>
 struct Smem {
   T *C0, *C1, *C2, *RH;  // ring 3: mass fractions and total density
@@ -169,6 +451,19 @@ __host__ __device__ inline size_t smem_bytes(int TX, int TY) {
                n1 = (size_t)(TX + 2) * (TY + 2);
   return (4 * n3 + 3 * n2 + 19 * n1) * sizeof(T) + ((n3 + 15) & ~(size_t)15);
 }
+
+template <typename T>
+struct TileAcc {
+  const Smem<T> &L;
+  int p1, p3, W1, W3, N1;
+  __device__ bool solid(int dx, int dy) const { return L.FL[p3 + dx + dy * W3] & FL_SOLID; }
+  __device__ T f(int dir, int dx, int dy) const { return L.PF[dir * N1 + p1 + dx + dy * W1]; }
+  __device__ T R(int c, int dx, int dy) const { return L.PR[c * N1 + p1 + dx + dy * W1]; }
+  __device__ T C(int k, int dx, int dy) const {
+    const int q = p3 + dx + dy * W3;
+    return k == 0 ? L.C0[q] : (k == 1 ? L.C1[q] : L.C2[q]);
+  }
+};
 
 template <typename S, typename T, bool FIELDS>
 __global__ __launch_bounds__(kThreads) void step_fused(StepArgs<S, T> A) {
@@ -190,7 +485,7 @@ __global__ __launch_bounds__(kThreads) void step_fused(StepArgs<S, T> A) {
   const int tid = threadIdx.x;
   const T eps_g = A.eps_g;
 
-  for (int wi = A.work_begin + blockIdx.x; wi < A.work_end; wi += gridDim.x) {
+  for (int wi = A.work_begin + first_item(A.remap); wi < A.work_end; wi += A.remap ? A.work_end : gridDim.x) {
     const WorkItem wk = A.work[wi];
     const DomainDev &D = A.doms[wk.dom];
     const int x0 = wk.x0, y0 = wk.y0;
@@ -199,19 +494,15 @@ __global__ __launch_bounds__(kThreads) void step_fused(StepArgs<S, T> A) {
     const S *Fin = A.fin + 9 * D.base;
     const int64_t P = D.plane;
 
-    // Phase A: C_k and rho on tile + 3 rings.
+    // Phase A: C_k and rho on tile + 3 rings (with the wetting fill at the fill nodes).
     for (int q = tid; q < N3; q += kThreads) {
       const int lx = q % W3, ly = q / W3;
       const int64_t li = node_index(x0 - 3 + lx, y0 - 3 + ly, D);
       const uint8_t fl = flags[li];
-      const T a = Rin[li], b = Rin[P + li], c = Rin[2 * P + li];
+      T v[4];
+      node_composition<T>(fl, Rin[li], Rin[P + li], Rin[2 * P + li], A.fillC, v);
       L.FL[q] = fl;
-      if (fl & FL_SOLID) {  // the partial densities of solid nodes hold the filled C (rho = 1)
-        L.C0[q] = a; L.C1[q] = b; L.C2[q] = c; L.RH[q] = T(1);
-      } else {
-        const T r = a + b + c;
-        L.C0[q] = a / r; L.C1[q] = b / r; L.C2[q] = c / r; L.RH[q] = r;
-      }
+      L.C0[q] = v[0]; L.C1[q] = v[1]; L.C2[q] = v[2]; L.RH[q] = v[3];
     }
     __syncthreads();
 
@@ -219,156 +510,76 @@ __global__ __launch_bounds__(kThreads) void step_fused(StepArgs<S, T> A) {
     for (int q = tid; q < N2; q += kThreads) {
       const int lx = q % W2, ly = q / W2;
       const int p3 = (lx + 1) + (ly + 1) * W3;
+      const int off[9] = {0, 1, W3, -1, -W3, 1 + W3, -1 + W3, -1 - W3, 1 - W3};
       T g[3][2];
       const T *Cs[3] = {L.C0, L.C1, L.C2};
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
-        const T *c = Cs[k];
-        // 3 * sum_a w_a C(x + e_a) e_a
-        const T gx = T(1.0 / 3.0) * (c[p3 + 1] - c[p3 - 1]) +
-                     T(1.0 / 12.0) * (c[p3 + 1 + W3] - c[p3 - 1 + W3] - c[p3 - 1 - W3] + c[p3 + 1 - W3]);
-        const T gy = T(1.0 / 3.0) * (c[p3 + W3] - c[p3 - W3]) +
-                     T(1.0 / 12.0) * (c[p3 + 1 + W3] + c[p3 - 1 + W3] - c[p3 - 1 - W3] - c[p3 + 1 - W3]);
-        g[k][0] = gx;
-        g[k][1] = gy;
+        T c9[9];
+#pragma unroll
+        for (int a = 0; a < 9; ++a) c9[a] = Cs[k][p3 + off[a]];
+        grad9(c9, g[k][0], g[k][1]);
       }
       const T cc[3] = {L.C0[p3], L.C1[p3], L.C2[p3]};
-      const T rho = L.RH[p3];
-      T txx = 0, txy = 0, tyy = 0;
-      T nrm[6];
-      const int pk[3] = {0, 0, 1}, pl[3] = {1, 2, 2};
-#pragma unroll
-      for (int pr = 0; pr < 3; ++pr) {
-        const int k = pk[pr], l = pl[pr];
-        const T Gx = cc[l] * g[k][0] - cc[k] * g[l][0];
-        const T Gy = cc[l] * g[k][1] - cc[k] * g[l][1];
-        const T mag = sqrt(Gx * Gx + Gy * Gy);
-        const T rk = cc[k] * rho, rl = cc[l] * rho;
-        const T Akl = fmin(fmax(T(1e6) * rk * rl, T(0)), T(1));
-        if (mag > eps_g) {
-          const T nx = Gx / mag, ny = Gy / mag;
-          const T coef = (T)D.sig[pr] * Akl * mag;
-          txx += coef * (T(1) - nx * nx);
-          txy += coef * (-nx * ny);
-          tyy += coef * (T(1) - ny * ny);
-          nrm[2 * pr] = nx;
-          nrm[2 * pr + 1] = ny;
-        } else {
-          nrm[2 * pr] = T(0);
-          nrm[2 * pr + 1] = T(0);
-        }
-      }
+      T txx, txy, tyy, nrm[6];
+      pair_stress(cc, g, L.RH[p3], D, eps_g, txx, txy, tyy, nrm);
       L.Txx[q] = txx; L.Txy[q] = txy; L.Tyy[q] = tyy;
       if (lx >= 1 && lx <= W2 - 2 && ly >= 1 && ly <= H2 - 2) {
         const int p1 = (lx - 1) + (ly - 1) * W1;
 #pragma unroll
-        for (int c = 0; c < 6; ++c) L.N[(c) * N1 + p1] = nrm[c];
+        for (int c = 0; c < 6; ++c) L.N[c * N1 + p1] = nrm[c];
       }
     }
     __syncthreads();
 
-    // Phase C: force, velocity, MRT collision and recolouring parameters on tile + 1 ring.
-    for (int q = tid; q < N1; q += kThreads) {
+    // Phase C: force, velocity, MRT collision and recolouring vectors on tile + 1 ring.
+    auto phase_c = [&](int q) {
       const int lx = q % W1, ly = q / W1;
       const int p2 = (lx + 1) + (ly + 1) * W2;
       const int p3 = (lx + 2) + (ly + 2) * W3;
-      if (L.FL[p3] & FL_SOLID) continue;
+      if (L.FL[p3] & FL_SOLID) return;
       const bool inside = lx >= 1 && lx <= TX && ly >= 1 && ly <= TY;
-      if (FIELDS && !inside) continue;
+      if (FIELDS && !inside) return;
       const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
       // Zou-He ghost columns are never streaming sources; off-grid rows are flagged solid.
-      if (D.bcx == BCX_ZOUHE && (gx < 0 || gx >= D.nx)) continue;
-      if (FIELDS && (gx >= D.nx || gy >= D.ny)) continue;
-      // F_s = div T, Eq. (12) on the stress components.
-      T Fx, Fy;
-      {
-        const T *xx = L.Txx, *xy = L.Txy, *yy = L.Tyy;
-        const int e = p2 + 1, w = p2 - 1, n = p2 + W2, s = p2 - W2;
-        const int ne = n + 1, nw = n - 1, sw = s - 1, se = s + 1;
-        Fx = T(1.0 / 3.0) * (xx[e] - xx[w]) + T(1.0 / 3.0) * (xy[n] - xy[s]) +
-             T(1.0 / 12.0) * (xx[ne] - xx[nw] - xx[sw] + xx[se] + xy[ne] + xy[nw] - xy[sw] - xy[se]);
-        Fy = T(1.0 / 3.0) * (xy[e] - xy[w]) + T(1.0 / 3.0) * (yy[n] - yy[s]) +
-             T(1.0 / 12.0) * (xy[ne] - xy[nw] - xy[sw] + xy[se] + yy[ne] + yy[nw] - yy[sw] - yy[se]);
-      }
-      const int64_t li = node_index(gx, gy, D);
-      T f[9];
+      if (D.bcx == BCX_ZOUHE && (gx < 0 || gx >= D.nx)) return;
+      if (FIELDS && (gx >= D.nx || gy >= D.ny)) return;
+      const int off2[9] = {0, 1, W2, -1, -W2, 1 + W2, -1 + W2, -1 - W2, 1 - W2};
+      T xx[9], xy[9], yy[9];
 #pragma unroll
-      for (int a = 0; a < 9; ++a) f[a] = load_s<S, T>(Fin + a * P + li);
-      // moments of the shifted distribution (M of Eq. 4 applied to f - w)
-      const T s14 = f[1] + f[2] + f[3] + f[4], s58 = f[5] + f[6] + f[7] + f[8];
-      const T drho = f[0] + s14 + s58;
-      const T m1 = -T(4) * f[0] - s14 + T(2) * s58;
-      const T m2 = T(4) * f[0] - T(2) * s14 + s58;
-      const T jx = f[1] - f[3] + f[5] - f[6] - f[7] + f[8];
-      const T m4 = -T(2) * f[1] + T(2) * f[3] + f[5] - f[6] - f[7] + f[8];
-      const T jy = f[2] - f[4] + f[5] + f[6] - f[7] - f[8];
-      const T m6 = -T(2) * f[2] + T(2) * f[4] + f[5] + f[6] - f[7] - f[8];
-      const T m7 = f[1] - f[2] + f[3] - f[4];
-      const T m8 = f[5] - f[6] + f[7] - f[8];
-      const T rho = T(1) + drho;
-      Fx += rho * (T)D.g[0];
-      Fy += rho * (T)D.g[1];
-      const T irho = T(1) / rho;
-      const T ux = (jx + T(0.5) * Fx) * irho, uy = (jy + T(0.5) * Fy) * irho;  // Eq. (11)
+      for (int a = 0; a < 9; ++a) {
+        xx[a] = L.Txx[p2 + off2[a]];
+        xy[a] = L.Txy[p2 + off2[a]];
+        yy[a] = L.Tyy[p2 + off2[a]];
+      }
+      T Fx, Fy;
+      div_stress(xx, xy, yy, Fx, Fy);
+      T f[9];
+      {
+        const int64_t li = node_index(gx, gy, D);
+#pragma unroll
+        for (int a = 0; a < 9; ++a) f[a] = load_s<S, T>(Fin + a * P + li);
+      }
       const T r0 = L.C0[p3] * L.RH[p3], r1 = L.C1[p3] * L.RH[p3], r2 = L.C2[p3] * L.RH[p3];
+      T fd[9], ux, uy;
+      collide_shifted(f, Fx, Fy, r0, r1, r2, D, fd, ux, uy);
       if (FIELDS) {
         const int64_t o = (int64_t)gy * D.nx + gx;
         const int64_t n = (int64_t)D.nx * D.ny;
-        if (A.out_u) {
-          A.out_u[o] = ux;
-          A.out_u[n + o] = uy;
-        }
-        if (A.out_force) {
-          A.out_force[o] = Fx;
-          A.out_force[n + o] = Fy;
-        }
-        continue;
+        if (A.out_u) { A.out_u[o] = ux; A.out_u[n + o] = uy; }
+        if (A.out_force) { A.out_force[o] = Fx; A.out_force[n + o] = Fy; }
+        return;
       }
-      // Eq. (7): tau = 1/2 + 3 / sum_k rho_k / mu_k; Eq. (6) rates.
-      const T tau = T(0.5) + T(3) / (r0 / (T)D.nu[0] + r1 / (T)D.nu[1] + r2 / (T)D.nu[2]);
-      const T s1 = T(1) / tau;
-      const T s4 = T(8) * (T(2) - s1) / (T(8) - s1);
-      const T uu = ux * ux + uy * uy;
-      const T ruu = rho * uu;
-      const T uF = ux * Fx + uy * Fy;
-      const T h1 = T(1) - T(0.5) * s1, h4 = T(1) - T(0.5) * s4;
-      // Delta_i = S_i (m_i - meq_i) - (1 - S_i/2) mF_i, scaled by diag(M M^T)^-1
-      const T d1 = (s1 * (m1 - (-T(2) * drho + T(3) * ruu)) - h1 * T(6) * uF) * T(1.0 / 36.0);
-      const T d2 = (s1 * (m2 - (drho - T(3) * ruu)) + h1 * T(6) * uF) * T(1.0 / 36.0);
-      const T d3 = -Fx * T(1.0 / 6.0);
-      const T d4 = (s4 * (m4 + rho * ux) + h4 * Fx) * T(1.0 / 12.0);
-      const T d5 = -Fy * T(1.0 / 6.0);
-      const T d6 = (s4 * (m6 + rho * uy) + h4 * Fy) * T(1.0 / 12.0);
-      const T d7 = (s1 * (m7 - rho * (ux * ux - uy * uy)) - h1 * T(2) * (ux * Fx - uy * Fy)) * T(0.25);
-      const T d8 = (s1 * (m8 - rho * ux * uy) - h1 * (ux * Fy + uy * Fx)) * T(0.25);
-      // f' = f - M^T d
-      T fd[9];
-      fd[0] = f[0] - (-T(4) * d1 + T(4) * d2);
-      fd[1] = f[1] - (-d1 - T(2) * d2 + d3 - T(2) * d4 + d7);
-      fd[2] = f[2] - (-d1 - T(2) * d2 + d5 - T(2) * d6 - d7);
-      fd[3] = f[3] - (-d1 - T(2) * d2 - d3 + T(2) * d4 + d7);
-      fd[4] = f[4] - (-d1 - T(2) * d2 - d5 + T(2) * d6 - d7);
-      fd[5] = f[5] - (T(2) * d1 + d2 + d3 + d4 + d5 + d6 + d8);
-      fd[6] = f[6] - (T(2) * d1 + d2 - d3 - d4 + d5 + d6 - d8);
-      fd[7] = f[7] - (T(2) * d1 + d2 - d3 - d4 - d5 - d6 + d8);
-      fd[8] = f[8] - (T(2) * d1 + d2 + d3 + d4 - d5 - d6 - d8);
 #pragma unroll
-      for (int a = 0; a < 9; ++a) L.PF[(a) * N1 + q] = fd[a];
-      // Recolouring, Eq. (13)-(15): R_1, R_2 (R_3 = -R_1 - R_2).
-      const T rt = L.RH[p3];
-      const T irt = T(1) / rt;
-      T r3 = T(35) * r0 * r1 * r2 * irt * irt * irt;
-      r3 = fmin(fmax(r3, T(0)), T(1));
-      const T b0 = (T)D.beta0;
-      const T b12 = b0 + b0 * r3 * (T)D.gX[0];
-      const T b13 = b0 + b0 * r3 * (T)D.gX[1];
-      const T b23 = b0 + b0 * r3 * (T)D.gX[2];
-      const T a12 = b12 * r0 * r1 * irt, a13 = b13 * r0 * r2 * irt, a23 = b23 * r1 * r2 * irt;
-      L.PR[(0) * N1 + q] = a12 * L.N[(0) * N1 + q] + a13 * L.N[(2) * N1 + q];
-      L.PR[(1) * N1 + q] = a12 * L.N[(1) * N1 + q] + a13 * L.N[(3) * N1 + q];
-      L.PR[(2) * N1 + q] = -a12 * L.N[(0) * N1 + q] + a23 * L.N[(4) * N1 + q];
-      L.PR[(3) * N1 + q] = -a12 * L.N[(1) * N1 + q] + a23 * L.N[(5) * N1 + q];
-    }
+      for (int a = 0; a < 9; ++a) L.PF[a * N1 + q] = fd[a];
+      T nrm[6], Rv[4];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) nrm[c] = L.N[c * N1 + q];
+      recolour_R(r0, r1, r2, L.RH[p3], nrm, D, Rv);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) L.PR[c * N1 + q] = Rv[c];
+    };
+    for (int q = tid; q < N1; q += kThreads) phase_c(q);
     if (FIELDS) {
       // partial densities (or filled C) of the tile
       for (int q = tid; q < TX * TY; q += kThreads) {
@@ -378,7 +589,12 @@ __global__ __launch_bounds__(kThreads) void step_fused(StepArgs<S, T> A) {
         const int64_t li = plane_index(gx, gy, D.pitch);
         const int64_t o = (int64_t)gy * D.nx + gx, n = (int64_t)D.nx * D.ny;
         const bool solid = flags[li] & FL_SOLID;
-        for (int k = 0; k < 3; ++k) A.out_rho[k * n + o] = Rin[k * P + li];
+        const int p3 = (lx + 3) + (ly + 3) * W3;
+        if (solid) {  // the filled C (zero at solid nodes that are not filled)
+          A.out_rho[o] = L.C0[p3]; A.out_rho[n + o] = L.C1[p3]; A.out_rho[2 * n + o] = L.C2[p3];
+        } else {
+          for (int k = 0; k < 3; ++k) A.out_rho[k * n + o] = Rin[k * P + li];
+        }
         if (solid) {
           if (A.out_u) { A.out_u[o] = 0; A.out_u[n + o] = 0; }
           if (A.out_force) { A.out_force[o] = 0; A.out_force[n + o] = 0; }
@@ -400,123 +616,175 @@ __global__ __launch_bounds__(kThreads) void step_fused(StepArgs<S, T> A) {
       const int p1 = (lx + 1) + (ly + 1) * W1;
       const int p3 = (lx + 3) + (ly + 3) * W3;
       const uint8_t fl = L.FL[p3];
-      if (fl & FL_SOLID) {
-#pragma unroll
-        for (int a = 0; a < 9; ++a) store_s<S, T>(Fout + a * P + li, T(0));
-        Rout[li] = T(0); Rout[P + li] = T(0); Rout[2 * P + li] = T(0);
-        continue;
-      }
-      T fo[9];
-      T ra = 0, rb = 0, rc = 0;
-      const T Cn[3] = {L.C0[p3], L.C1[p3], L.C2[p3]};
-      const IbbNode *ib = nullptr;
-      if ((fl & FL_CURVED) && D.n_ibb > 0) {
-        int lo = D.ibb_off, hi = D.ibb_off + D.n_ibb - 1;
-        while (lo < hi) {
-          const int mid = (lo + hi) >> 1;
-          if (A.ibb[mid].li < li) lo = mid + 1;
-          else hi = mid;
-        }
-        ib = &A.ibb[lo];
-      }
-#pragma unroll
-      for (int a = 0; a < 9; ++a) {
-        const int ex = lat_ex(a), ey = lat_ey(a);
-        const int sx = gx - ex;
-        if (D.bcx == BCX_ZOUHE && (sx < 0 || sx >= D.nx)) {  // set by the Zou-He rule below
-          fo[a] = 0;
-          continue;
-        }
-        const T w = wgt<T>(a);
-        const int s1 = p1 - ex - ey * W1, s3 = p3 - ex - ey * W3;
-        if (!(L.FL[s3] & FL_SOLID)) {
-          const T fs = L.PF[(a) * N1 + s1];
-          fo[a] = fs;
-          const T ft = fs + w;
-          const T Cs0 = L.C0[s3], Cs1 = L.C1[s3], Cs2 = L.C2[s3];
-          const T R1 = L.PR[(0) * N1 + s1] * ex + L.PR[(1) * N1 + s1] * ey;
-          const T R2 = L.PR[(2) * N1 + s1] * ex + L.PR[(3) * N1 + s1] * ey;
-          const T R3 = -(R1 + R2);
-          const T c0 = Cs0 * ft + w * R1, c1 = Cs1 * ft + w * R2, c2 = Cs2 * ft + w * R3;
-          const bool crossed = D.bcx == BCX_SWAP13 && (sx < 0 || sx >= D.nx);
-          if (crossed) { ra += c2; rb += c1; rc += c0; }
-          else { ra += c0; rb += c1; rc += c2; }
-        } else {
-          // the link x -> x - e_a ends in a solid node: bounce-back of the populations
-          // leaving x along -e_a (direction ab)
-          const int ab = lat_opp(a);
-          const T qd = ib ? (T)ib->q[a - 1] : T(0.5);
-          const int eax = -ex, eay = -ey;  // e_ab
-          const T fab = L.PF[(ab) * N1 + p1];
-          auto part = [&](int p1x, int p3x, int dir, int dx, int dy, T *out) {
-            const T fv = L.PF[(dir) * N1 + p1x] + w;
-            const T R1 = L.PR[(0) * N1 + p1x] * dx + L.PR[(1) * N1 + p1x] * dy;
-            const T R2 = L.PR[(2) * N1 + p1x] * dx + L.PR[(3) * N1 + p1x] * dy;
-            out[0] = L.C0[p3x] * fv + w * R1;
-            out[1] = L.C1[p3x] * fv + w * R2;
-            out[2] = L.C2[p3x] * fv + w * (-(R1 + R2));
-          };
-          T own_ab[3];
-          part(p1, p3, ab, eax, eay, own_ab);
-          const int n1 = p1 + ex + ey * W1, n3 = p3 + ex + ey * W3;
-          if (qd < T(0.5) && !(L.FL[n3] & FL_SOLID)) {
-            T nb_ab[3];
-            part(n1, n3, ab, eax, eay, nb_ab);
-            const T c1 = T(2) * qd, c2 = T(1) - T(2) * qd;
-            fo[a] = c1 * fab + c2 * L.PF[(ab) * N1 + n1];
-            ra += c1 * own_ab[0] + c2 * nb_ab[0];
-            rb += c1 * own_ab[1] + c2 * nb_ab[1];
-            rc += c1 * own_ab[2] + c2 * nb_ab[2];
-          } else if (qd < T(0.5)) {
-            fo[a] = fab;
-            ra += own_ab[0]; rb += own_ab[1]; rc += own_ab[2];
-          } else {
-            T own_a[3];
-            part(p1, p3, a, ex, ey, own_a);
-            const T c1 = T(1) / (T(2) * qd), c2 = T(1) - c1;
-            fo[a] = c1 * fab + c2 * L.PF[(a) * N1 + p1];
-            ra += c1 * own_ab[0] + c2 * own_a[0];
-            rb += c1 * own_ab[1] + c2 * own_a[1];
-            rc += c1 * own_ab[2] + c2 * own_a[2];
-          }
-        }
-      }
-      if (D.bcx == BCX_ZOUHE && (gx == 0 || gx == D.nx - 1)) {
-        // Zou-He non-equilibrium bounce-back on the total distribution (unshifted).
-        T ft[9];
-#pragma unroll
-        for (int a = 0; a < 9; ++a) ft[a] = fo[a] + wgt<T>(a);
-        if (gx == 0) {
-          const T u = (T)D.u_in;
-          const T rw = (ft[0] + ft[2] + ft[4] + T(2) * (ft[3] + ft[6] + ft[7])) / (T(1) - u);
-          ft[1] = ft[3] + T(2.0 / 3.0) * rw * u;
-          ft[5] = ft[7] - T(0.5) * (ft[2] - ft[4]) + rw * u / T(6);
-          ft[8] = ft[6] + T(0.5) * (ft[2] - ft[4]) + rw * u / T(6);
-          // incoming populations carry pure fluid 3
-          rc += ft[1] + ft[5] + ft[8];
-          fo[1] = ft[1] - wgt<T>(1);
-          fo[5] = ft[5] - wgt<T>(5);
-          fo[8] = ft[8] - wgt<T>(8);
-        } else {
-          const T ro = (T)D.rho_out;
-          const T ux = -T(1) + (ft[0] + ft[2] + ft[4] + T(2) * (ft[1] + ft[5] + ft[8])) / ro;
-          ft[3] = ft[1] - T(2.0 / 3.0) * ro * ux;
-          ft[7] = ft[5] + T(0.5) * (ft[2] - ft[4]) - ro * ux / T(6);
-          ft[6] = ft[8] - T(0.5) * (ft[2] - ft[4]) - ro * ux / T(6);
-          // unknown populations carry the node's own composition
-          ra += Cn[0] * ft[3]; rb += Cn[1] * ft[3]; rc += Cn[2] * ft[3];
-          ra += Cn[0] * ft[6]; rb += Cn[1] * ft[6]; rc += Cn[2] * ft[6];
-          ra += Cn[0] * ft[7]; rb += Cn[1] * ft[7]; rc += Cn[2] * ft[7];
-          fo[3] = ft[3] - wgt<T>(3);
-          fo[6] = ft[6] - wgt<T>(6);
-          fo[7] = ft[7] - wgt<T>(7);
-        }
-      }
+      if (fl & FL_SOLID) continue;  // solid slots keep their constant contents
+      TileAcc<T> acc{L, p1, p3, W1, W3, N1};
+      T fo[9], ra, rb, rc;
+      stream_node<T>(acc, gx, fl, li, D, A.ibb, fo, ra, rb, rc);
 #pragma unroll
       for (int a = 0; a < 9; ++a) store_s<S, T>(Fout + a * P + li, fo[a]);
       Rout[li] = ra;
       Rout[P + li] = rb;
       Rout[2 * P + li] = rc;
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Strip kernel: one work-group of NT threads owns a strip of NT-6 columns and marches up a
+// segment of rows.  Thread c holds column x0-3+c.  Per row r it loads C_k of row r (ring of 6
+// rows), forms the stress of row r-1 (ring of 3), collides row r-2 (ring of 3 rows of
+// post-collision data) and streams row r-3 into HBM, so every row is read once and halos in y
+// are reused from LDS; only the 6 halo columns of the strip are recomputed.
+template <typename T>
+__host__ __device__ inline size_t strip_smem_bytes(int nt) {
+  return (size_t)nt * ((6 * 4 + 3 * 3 + 3 * 13) * sizeof(T) + 6);
+}
+
+template <typename T, int NT>
+struct StripAcc {
+  const T *Cr, *Pr;       // C ring [6][4][NT], post-collision ring [3][13][NT]
+  const uint8_t *Fr;      // flag ring [6][NT]
+  int c;                  // column
+  int cs[3], ps[3];       // C / post-collision ring slots of rows y-1, y, y+1
+  __device__ bool solid(int dx, int dy) const { return Fr[cs[dy + 1] * NT + c + dx] & FL_SOLID; }
+  __device__ T f(int dir, int dx, int dy) const { return Pr[(ps[dy + 1] * 13 + dir) * NT + c + dx]; }
+  __device__ T R(int k, int dx, int dy) const { return Pr[(ps[dy + 1] * 13 + 9 + k) * NT + c + dx]; }
+  __device__ T C(int k, int dx, int dy) const { return Cr[(cs[dy + 1] * 4 + k) * NT + c + dx]; }
+};
+
+__device__ __forceinline__ int mod_pos(int v, int m) {
+  const int r = v % m;
+  return r < 0 ? r + m : r;
+}
+
+template <typename S, typename T, int NT>
+__global__ __launch_bounds__(NT) void step_strip(StepArgs<S, T> A) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T *Cr = reinterpret_cast<T *>(smem_raw);  // [6][4][NT]: C0, C1, C2, rho
+  T *Tr = Cr + 6 * 4 * NT;                  // [3][3][NT]: Txx, Txy, Tyy
+  T *Pr = Tr + 3 * 3 * NT;                  // [3][13][NT]: f'(9), R(4)
+  uint8_t *Fr = reinterpret_cast<uint8_t *>(Pr + 3 * 13 * NT);  // [6][NT]
+  const int c = threadIdx.x;
+  const T eps_g = A.eps_g;
+
+  for (int wi = A.work_begin + first_item(A.remap); wi < A.work_end; wi += A.remap ? A.work_end : gridDim.x) {
+    const WorkItem wk = A.work[wi];
+    const DomainDev &D = A.doms[wk.dom];
+    const int x0 = wk.x0, x1 = wk.x1, y0 = wk.y0, y1 = wk.y1;
+    const uint8_t *flags = A.flags + D.base;
+    const T *Rin = A.rin + 3 * D.base;
+    const S *Fin = A.fin + 9 * D.base;
+    T *Rout = A.rout + 3 * D.base;
+    S *Fout = A.fout + 9 * D.base;
+    const int64_t P = D.plane;
+    const int gx = x0 - 3 + c;
+    const int gxm = D.bcx == BCX_ZOUHE ? min(max(gx, 0), D.nx - 1) : wrap_small(gx, D.nx);
+    const int yend = min(y1, D.ny);
+
+    for (int r = y0 - 3; r <= y1 + 2; ++r) {
+      // Stage A: C_k and rho of row r.
+      {
+        const int gy = D.yper ? wrap_small(r, D.ny) : min(max(r, -2), D.ny + 1);
+        const int64_t li = plane_index(gxm, gy, D.pitch);
+        const uint8_t fl = flags[li];
+        T v[4];
+        node_composition<T>(fl, Rin[li], Rin[P + li], Rin[2 * P + li], A.fillC, v);
+        const int sl = mod_pos(r, 6);
+        T *cr = Cr + sl * 4 * NT;
+        Fr[sl * NT + c] = fl;
+        cr[c] = v[0]; cr[NT + c] = v[1]; cr[2 * NT + c] = v[2]; cr[3 * NT + c] = v[3];
+      }
+      __syncthreads();
+      // Stage B: stress of row r-1.
+      if (r - 1 >= y0 - 2 && c >= 1 && c < NT - 1) {
+        const int sm = mod_pos(r - 2, 6), s0 = mod_pos(r - 1, 6), sp = mod_pos(r, 6);
+        T g[3][2];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const T *lo = Cr + (sm * 4 + k) * NT + c, *mi = Cr + (s0 * 4 + k) * NT + c, *hi = Cr + (sp * 4 + k) * NT + c;
+          const T c9[9] = {mi[0], mi[1], hi[0], mi[-1], lo[0], hi[1], hi[-1], lo[-1], lo[1]};
+          grad9(c9, g[k][0], g[k][1]);
+        }
+        const T *mi = Cr + s0 * 4 * NT + c;
+        const T cc[3] = {mi[0], mi[NT], mi[2 * NT]};
+        T txx, txy, tyy, nrm[6];
+        pair_stress(cc, g, mi[3 * NT], D, eps_g, txx, txy, tyy, nrm);
+        T *tr = Tr + mod_pos(r - 1, 3) * 3 * NT;
+        tr[c] = txx; tr[NT + c] = txy; tr[2 * NT + c] = tyy;
+      }
+      __syncthreads();
+      // Stage C: collision and recolouring vectors of row r-2.
+      const int yc = r - 2;
+      if (yc >= y0 - 1 && yc <= y1 && c >= 2 && c < NT - 2) {
+        const int s0 = mod_pos(yc, 6);
+        const uint8_t fl = Fr[s0 * NT + c];
+        const bool ghost = D.bcx == BCX_ZOUHE && (gx < 0 || gx >= D.nx);
+        if (!(fl & FL_SOLID) && !ghost) {
+          const int tm = mod_pos(yc - 1, 3), t0 = mod_pos(yc, 3), tp = mod_pos(yc + 1, 3);
+          T xx[9], xy[9], yy[9];
+          const T *trs[3] = {Tr + tm * 3 * NT + c, Tr + t0 * 3 * NT + c, Tr + tp * 3 * NT + c};
+#pragma unroll
+          for (int q = 0; q < 3; ++q) {
+            const T *lo = trs[0] + q * NT, *mi = trs[1] + q * NT, *hi = trs[2] + q * NT;
+            const T v9[9] = {mi[0], mi[1], hi[0], mi[-1], lo[0], hi[1], hi[-1], lo[-1], lo[1]};
+#pragma unroll
+            for (int a = 0; a < 9; ++a) (q == 0 ? xx : (q == 1 ? xy : yy))[a] = v9[a];
+          }
+          T Fx, Fy;
+          div_stress(xx, xy, yy, Fx, Fy);
+          // normals of row yc (gradients again, from the C ring)
+          const int cm = mod_pos(yc - 1, 6), cp = mod_pos(yc + 1, 6);
+          T g[3][2];
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            const T *lo = Cr + (cm * 4 + k) * NT + c, *mi = Cr + (s0 * 4 + k) * NT + c, *hi = Cr + (cp * 4 + k) * NT + c;
+            const T c9[9] = {mi[0], mi[1], hi[0], mi[-1], lo[0], hi[1], hi[-1], lo[-1], lo[1]};
+            grad9(c9, g[k][0], g[k][1]);
+          }
+          const T *mi = Cr + s0 * 4 * NT + c;
+          const T cc[3] = {mi[0], mi[NT], mi[2 * NT]};
+          const T rt = mi[3 * NT];
+          T txx, txy, tyy, nrm[6];
+          pair_stress(cc, g, rt, D, eps_g, txx, txy, tyy, nrm);
+          const int gy = D.yper ? wrap_small(yc, D.ny) : yc;
+          const int64_t li = plane_index(gxm, gy, D.pitch);
+          T f[9];
+#pragma unroll
+          for (int a = 0; a < 9; ++a) f[a] = load_s<S, T>(Fin + a * P + li);
+          const T r0 = cc[0] * rt, r1 = cc[1] * rt, r2 = cc[2] * rt;
+          T fd[9], ux, uy, Rv[4];
+          collide_shifted(f, Fx, Fy, r0, r1, r2, D, fd, ux, uy);
+          recolour_R(r0, r1, r2, rt, nrm, D, Rv);
+          T *pr = Pr + mod_pos(yc, 3) * 13 * NT + c;
+#pragma unroll
+          for (int a = 0; a < 9; ++a) pr[a * NT] = fd[a];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) pr[(9 + q) * NT] = Rv[q];
+        }
+      }
+      __syncthreads();
+      // Stage D: stream row r-3 into HBM.
+      const int yd = r - 3;
+      const int x = x0 + c - 3;
+      if (yd >= y0 && yd < yend && c >= 3 && c < NT - 3 && x < x1) {
+        const int64_t li = plane_index(x, yd, D.pitch);
+        const int s0 = mod_pos(yd, 6);
+        const uint8_t fl = Fr[s0 * NT + c];
+        if (!(fl & FL_SOLID)) {
+          StripAcc<T, NT> acc;
+          acc.Cr = Cr; acc.Pr = Pr; acc.Fr = Fr; acc.c = c;
+          acc.cs[0] = mod_pos(yd - 1, 6); acc.cs[1] = s0; acc.cs[2] = mod_pos(yd + 1, 6);
+          acc.ps[0] = mod_pos(yd - 1, 3); acc.ps[1] = mod_pos(yd, 3); acc.ps[2] = mod_pos(yd + 1, 3);
+          T fo[9], ra, rb, rc;
+          stream_node<T>(acc, x, fl, li, D, A.ibb, fo, ra, rb, rc);
+#pragma unroll
+          for (int a = 0; a < 9; ++a) store_s<S, T>(Fout + a * P + li, fo[a]);
+          Rout[li] = ra;
+          Rout[P + li] = rb;
+          Rout[2 * P + li] = rc;
+        }
+      }
     }
     __syncthreads();
   }
@@ -571,18 +839,21 @@ __global__ void mass_final(const double *partial, const int *chunk_first, int n_
 template <typename T>
 hipError_t launch_fill(const FillArgs<T> &a, hipStream_t s) {
   if (a.n_fill <= 0) return hipSuccess;
-  const int blocks = (a.n_fill + kThreads - 1) / kThreads;
-  hipLaunchKernelGGL(wet_fill<T>, dim3(blocks), dim3(kThreads), 0, s, a);
+  hipLaunchKernelGGL(wet_fill<T>, dim3((4 * a.n_fill + kThreads - 1) / kThreads), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
 
 template <typename S, typename T>
-hipError_t launch_step(const StepArgs<S, T> &a, int grid, bool fields, hipStream_t s) {
-  const size_t sm = smem_bytes<T>(a.tile_x, a.tile_y);
-  if (fields)
-    hipLaunchKernelGGL((step_fused<S, T, true>), dim3(grid), dim3(kThreads), sm, s, a);
-  else
-    hipLaunchKernelGGL((step_fused<S, T, false>), dim3(grid), dim3(kThreads), sm, s, a);
+hipError_t launch_step(const StepArgs<S, T> &a, int grid, int mode, bool fields, hipStream_t s) {
+  if (fields) {
+    hipLaunchKernelGGL((step_fused<S, T, true>), dim3(grid), dim3(kThreads), smem_bytes<T>(a.tile_x, a.tile_y), s, a);
+  } else if (mode == MODE_TILE) {
+    hipLaunchKernelGGL((step_fused<S, T, false>), dim3(grid), dim3(kThreads), smem_bytes<T>(a.tile_x, a.tile_y), s, a);
+  } else if (mode == MODE_STRIP128) {
+    hipLaunchKernelGGL((step_strip<S, T, 128>), dim3(grid), dim3(128), strip_smem_bytes<T>(128), s, a);
+  } else {
+    hipLaunchKernelGGL((step_strip<S, T, 256>), dim3(grid), dim3(256), strip_smem_bytes<T>(256), s, a);
+  }
   return hipGetLastError();
 }
 
@@ -601,6 +872,17 @@ hipError_t init_kernel_attributes() {
   LBM3_ATTR(__half, float, false)
   LBM3_ATTR(__half, float, true)
 #undef LBM3_ATTR
+#define LBM3_ATTR2(S, T, N)                                                                   \
+  r = hipFuncSetAttribute((const void *)step_strip<S, T, N>,                                  \
+                          hipFuncAttributeMaxDynamicSharedMemorySize, lim);                   \
+  if (r != hipSuccess) e = r;
+  LBM3_ATTR2(double, double, 128)
+  LBM3_ATTR2(double, double, 256)
+  LBM3_ATTR2(float, float, 128)
+  LBM3_ATTR2(float, float, 256)
+  LBM3_ATTR2(__half, float, 128)
+  LBM3_ATTR2(__half, float, 256)
+#undef LBM3_ATTR2
   return e;
 }
 
@@ -611,15 +893,17 @@ hipError_t launch_mass(const MassArgs<T> &a, int n_chunks, int n_dom, double *ou
   return hipGetLastError();
 }
 
-size_t step_smem_bytes(int precision, int tx, int ty) {
-  return precision == 0 ? smem_bytes<double>(tx, ty) : smem_bytes<float>(tx, ty);
+size_t step_smem_bytes(int precision, int mode, int tx, int ty) {
+  if (mode == MODE_TILE) return precision == 0 ? smem_bytes<double>(tx, ty) : smem_bytes<float>(tx, ty);
+  const int nt = mode == MODE_STRIP128 ? 128 : 256;
+  return precision == 0 ? strip_smem_bytes<double>(nt) : strip_smem_bytes<float>(nt);
 }
 
+template hipError_t launch_step<double, double>(const StepArgs<double, double> &, int, int, bool, hipStream_t);
+template hipError_t launch_step<float, float>(const StepArgs<float, float> &, int, int, bool, hipStream_t);
+template hipError_t launch_step<__half, float>(const StepArgs<__half, float> &, int, int, bool, hipStream_t);
 template hipError_t launch_fill<double>(const FillArgs<double> &, hipStream_t);
 template hipError_t launch_fill<float>(const FillArgs<float> &, hipStream_t);
-template hipError_t launch_step<double, double>(const StepArgs<double, double> &, int, bool, hipStream_t);
-template hipError_t launch_step<float, float>(const StepArgs<float, float> &, int, bool, hipStream_t);
-template hipError_t launch_step<__half, float>(const StepArgs<__half, float> &, int, bool, hipStream_t);
 template hipError_t launch_mass<double>(const MassArgs<double> &, int, int, double *, hipStream_t);
 template hipError_t launch_mass<float>(const MassArgs<float> &, int, int, double *, hipStream_t);
 

@@ -23,7 +23,7 @@ PRECISIONS = {"f64": LBM3_F64, "f32": LBM3_F32, "f16": LBM3_F32_STORE_F16}
 
 # Symbols declared in include/lbm3.h.
 ABI_SYMBOLS = [
-    "lbm3_workspace_bytes", "lbm3_create", "lbm3_step", "lbm3_fill", "lbm3_fields", "lbm3_mass",
+    "lbm3_workspace_bytes", "lbm3_create", "lbm3_step", "lbm3_fields", "lbm3_mass",
     "lbm3_state_bytes", "lbm3_get_state", "lbm3_set_state", "lbm3_kernel_times", "lbm3_autotune",
     "lbm3_query", "lbm3_last_error", "lbm3_plan_error", "lbm3_status_string", "lbm3_destroy",
 ]
@@ -44,9 +44,12 @@ class lbm3_domain(C.Structure):
 class lbm3_options(C.Structure):
     _fields_ = [
         ("precision", C.c_int32), ("graph_block_steps", C.c_int32), ("beta0", C.c_double),
-        ("tile_x", C.c_int32), ("tile_y", C.c_int32), ("persistent_blocks", C.c_int32),
-        ("reserved", C.c_int32),
+        ("kernel", C.c_int32), ("tile_x", C.c_int32), ("tile_y", C.c_int32),
+        ("persistent_blocks", C.c_int32),
     ]
+
+
+KERNELS = {"tile": 0, "strip128": 1, "strip256": 2, "auto": -1}
 
 
 class Lbm3Error(RuntimeError):
@@ -71,7 +74,6 @@ def library() -> C.CDLL:
             "lbm3_workspace_bytes": (i32, [dom_p, i32, opt_p, szp]),
             "lbm3_create": (i32, [dom_p, i32, opt_p, vp, C.c_size_t, vp, C.POINTER(vp)]),
             "lbm3_step": (i32, [vp, i32]),
-            "lbm3_fill": (i32, [vp]),
             "lbm3_fields": (i32, [vp, i32, vp, vp, vp, i32]),
             "lbm3_mass": (i32, [vp, dp]),
             "lbm3_state_bytes": (i32, [vp, szp]),
@@ -120,14 +122,15 @@ class DomainArgs:
         self.n = len(workloads)
 
 
-def make_options(precision="f32", graph_block_steps=0, beta0=0.0, tile=None, persistent_blocks=0):
+def make_options(precision="f32", graph_block_steps=0, beta0=0.0, tile=None, persistent_blocks=0,
+                 kernel="tile"):
     o = lbm3_options()
     o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     o.graph_block_steps = int(graph_block_steps)
     o.beta0 = float(beta0)
+    o.kernel = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
     o.tile_x, o.tile_y = (0, 0) if tile is None else (int(tile[0]), int(tile[1]))
     o.persistent_blocks = int(persistent_blocks)
-    o.reserved = 0
     return o
 
 
@@ -157,10 +160,6 @@ def lbm3_step(ctx, nsteps: int) -> None:
     _check(library().lbm3_step(ctx, int(nsteps)), ctx)
 
 
-def lbm3_fill(ctx) -> None:
-    _check(library().lbm3_fill(ctx), ctx)
-
-
 def lbm3_fields(ctx, domain: int, rho_ptr: int, u_ptr: int, force_ptr: int, dtype: int) -> None:
     _check(library().lbm3_fields(ctx, int(domain), C.c_void_p(rho_ptr), C.c_void_p(u_ptr or None),
                                  C.c_void_p(force_ptr or None), int(dtype)), ctx)
@@ -187,15 +186,16 @@ def lbm3_set_state(ctx, src_ptr: int) -> None:
 
 
 def lbm3_kernel_times(ctx, nsteps: int):
+    """(ms per fill launch, ms per fused-step launch)."""
     a, b = C.c_double(0), C.c_double(0)
     _check(library().lbm3_kernel_times(ctx, int(nsteps), C.byref(a), C.byref(b)), ctx)
     return a.value, b.value
 
 
 def lbm3_autotune(ctx, steps: int):
-    t = (C.c_int32 * 2)()
+    t = (C.c_int32 * 3)()
     _check(library().lbm3_autotune(ctx, int(steps), t), ctx)
-    return int(t[0]), int(t[1])
+    return int(t[0]), int(t[1]), int(t[2])
 
 
 def lbm3_query(ctx, key: int) -> float:
@@ -214,7 +214,7 @@ class Simulation:
     """Domains advanced together on one GPU by liblbm3."""
 
     def __init__(self, workloads, precision="f32", graph_block_steps=0, tile=None,
-                 persistent_blocks=0, beta0=0.0, device="cuda:0"):
+                 persistent_blocks=0, beta0=0.0, device="cuda:0", kernel="tile"):
         import torch
 
         if not isinstance(workloads, (list, tuple)):
@@ -223,7 +223,7 @@ class Simulation:
         self.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         self.device = torch.device(device)
         self.domains = DomainArgs(self.workloads)
-        self.options = make_options(precision, graph_block_steps, beta0, tile, persistent_blocks)
+        self.options = make_options(precision, graph_block_steps, beta0, tile, persistent_blocks, kernel)
         nbytes = lbm3_workspace_bytes(self.domains, self.options)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self.stream = torch.cuda.current_stream(self.device)
@@ -238,9 +238,6 @@ class Simulation:
 
     def step(self, n: int = 1) -> None:
         lbm3_step(self.ctx, n)
-
-    def fill(self) -> None:
-        lbm3_fill(self.ctx)
 
     def fields(self, domain: int = 0, velocity=True, force=True) -> Dict[str, "object"]:
         import torch
