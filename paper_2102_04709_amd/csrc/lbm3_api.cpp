@@ -37,10 +37,9 @@ struct Candidate {
   int kernel, tx, ty;
 };
 // Candidate configurations of the fused kernel (the autotuner picks among them).
-const Candidate kCands[] = {{MODE_TILE, 32, 8},      {MODE_TILE, 64, 4},      {MODE_TILE, 64, 8},
-                            {MODE_TILE, 32, 16},     {MODE_TILE, 16, 16},     {MODE_TILE, 128, 4},
-                            {MODE_STRIP128, 0, 32},  {MODE_STRIP128, 0, 64},  {MODE_STRIP128, 0, 128},
-                            {MODE_STRIP256, 0, 32},  {MODE_STRIP256, 0, 64},  {MODE_STRIP256, 0, 128}};
+const Candidate kCands[] = {{MODE_TILE, 32, 8},     {MODE_TILE, 16, 16},    {MODE_TILE, 64, 4},
+                            {MODE_TILE, 64, 8},     {MODE_STRIP128, 0, 32}, {MODE_STRIP256, 0, 32},
+                            {MODE_STRIP256, 0, 64}};
 const int kMinTileArea = 256;
 const int kMinStripRows = 8;
 const int kFieldTileX = 32, kFieldTileY = 8;  // tile of the field export
@@ -297,9 +296,9 @@ bool plan(const lbm3_domain *d, int n, const lbm3_options *o, std::vector<DomHos
   if (o->tile_x < 0 || o->tile_y < 0 || o->graph_block_steps < 0 || o->persistent_blocks < 0) return err = "negative option", false;
   if (o->kernel <= 0 && (o->tile_x > 0 || o->tile_y > 0)) {
     const int area = o->tile_x * o->tile_y;
-    if (o->tile_x <= 0 || o->tile_y <= 0 || area < kMinTileArea || area > 4096 ||
+    if (o->tile_x <= 0 || o->tile_y <= 0 || area < kMinTileArea || !tile_supported(o->tile_x, o->tile_y) ||
         step_smem_bytes(o->precision, MODE_TILE, o->tile_x, o->tile_y) > 160 * 1024)
-      return err = "tile shape out of range (area 256..4096, LDS <= 160 KiB)", false;
+      return err = "tile shape not supported (32x8, 16x16, 64x4, 64x8 within 160 KiB of LDS)", false;
   }
   if (o->kernel > 0 && o->tile_y > 0 && o->tile_y < kMinStripRows) return err = "strip segments need at least 8 rows", false;
   const double beta0 = o->beta0 > 0 ? o->beta0 : 0.7;

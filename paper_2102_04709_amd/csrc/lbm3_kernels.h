@@ -58,6 +58,7 @@ hipError_t launch_step(const StepArgs<S, T> &a, int grid, int mode, bool fields,
 template <typename T>
 hipError_t launch_mass(const MassArgs<T> &a, int n_chunks, int n_dom, double *out, hipStream_t s);
 size_t step_smem_bytes(int precision, int mode, int tx, int ty);
+bool tile_supported(int tx, int ty);
 hipError_t init_kernel_attributes();
 
 }  // namespace lbm3

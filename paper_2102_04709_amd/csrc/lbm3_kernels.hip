@@ -36,6 +36,14 @@ __device__ __forceinline__ T wgt(int a) {
   return a == 0 ? T(4.0 / 9.0) : (a < 5 ? T(1.0 / 9.0) : T(1.0 / 36.0));
 }
 
+// Reciprocal: the hardware reciprocal (1 ulp) in FP32, an IEEE division in FP64.
+template <typename T>
+__device__ __forceinline__ T rcp(T x);
+template <>
+__device__ __forceinline__ float rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <>
+__device__ __forceinline__ double rcp<double>(double x) { return 1.0 / x; }
+
 template <typename S>
 __device__ __forceinline__ float to_f(S v);
 template <>
@@ -191,13 +199,40 @@ __device__ __forceinline__ void node_composition(uint8_t fl, T a, T b, T c, cons
     out[3] = T(1);
   } else {
     const T r = a + b + c;
-    out[0] = a / r; out[1] = b / r; out[2] = c / r; out[3] = r;
+    const T ir = rcp(r);
+    out[0] = a * ir; out[1] = b * ir; out[2] = c * ir; out[3] = r;
   }
 }
 
 // ------------------------------------------------------------------------------------------
 // Per-node pieces of the fused step, shared by the tile and the strip kernels.  Neighbour
 // values are passed in D2Q9 order c[a] = psi(x + e_a).
+
+// Per-domain constants in the compute type, read once per work item.
+template <typename T>
+struct KT {
+  T inu[3];  // 1 / nu_k
+  T sig[3];  // sigma12, sigma13, sigma23
+  T gX[3];   // g(X_kl) for the pairs 12, 13, 23
+  T b0, g0, g1, u_in, rho_out;
+};
+
+template <typename T>
+__device__ __forceinline__ KT<T> make_kt(const DomainDev &D) {
+  KT<T> K;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    K.inu[k] = (T)(1.0 / D.nu[k]);
+    K.sig[k] = (T)D.sig[k];
+    K.gX[k] = (T)D.gX[k];
+  }
+  K.b0 = (T)D.beta0;
+  K.g0 = (T)D.g[0];
+  K.g1 = (T)D.g[1];
+  K.u_in = (T)D.u_in;
+  K.rho_out = (T)D.rho_out;
+  return K;
+}
 
 // Eq. (12): (1/c_s^2) sum_a w_a psi(x + e_a) e_a.
 template <typename T>
@@ -210,7 +245,7 @@ __device__ __forceinline__ void grad9(const T *c, T &gx, T &gy) {
 // the factor 1/2 equals the sum over unordered pairs, since G_lk = -G_kl), and the pair normals
 // n_kl = G_kl / |G_kl| (zero when |G_kl| <= eps).
 template <typename T>
-__device__ __forceinline__ void pair_stress(const T cc[3], const T g[3][2], T rho, const DomainDev &D,
+__device__ __forceinline__ void pair_stress(const T cc[3], const T g[3][2], T rho, const KT<T> &K,
                                             T eps, T &txx, T &txy, T &tyy, T nrm[6]) {
   txx = txy = tyy = T(0);
   const int pk[3] = {0, 0, 1}, pl[3] = {1, 2, 2};
@@ -223,8 +258,9 @@ __device__ __forceinline__ void pair_stress(const T cc[3], const T g[3][2], T rh
     const T rk = cc[k] * rho, rl = cc[l] * rho;
     const T Akl = fmin(fmax(T(1e6) * rk * rl, T(0)), T(1));
     if (mag > eps) {
-      const T nx = Gx / mag, ny = Gy / mag;
-      const T coef = (T)D.sig[pr] * Akl * mag;
+      const T im = rcp(mag);
+      const T nx = Gx * im, ny = Gy * im;
+      const T coef = K.sig[pr] * Akl * mag;
       txx += coef * (T(1) - nx * nx);
       txy += coef * (-nx * ny);
       tyy += coef * (T(1) - ny * ny);
@@ -251,7 +287,7 @@ __device__ __forceinline__ void div_stress(const T *xx, const T *xy, const T *yy
 // the total force (the body acceleration times rho added).
 template <typename T>
 __device__ __forceinline__ void collide_shifted(const T f[9], T &Fx, T &Fy, T r0, T r1, T r2,
-                                                const DomainDev &D, T fd[9], T &ux, T &uy) {
+                                                const KT<T> &K, T fd[9], T &ux, T &uy) {
   const T s14 = f[1] + f[2] + f[3] + f[4], s58 = f[5] + f[6] + f[7] + f[8];
   const T drho = f[0] + s14 + s58;
   const T m1 = -T(4) * f[0] - s14 + T(2) * s58;
@@ -263,14 +299,15 @@ __device__ __forceinline__ void collide_shifted(const T f[9], T &Fx, T &Fy, T r0
   const T m7 = f[1] - f[2] + f[3] - f[4];
   const T m8 = f[5] - f[6] + f[7] - f[8];
   const T rho = T(1) + drho;
-  Fx += rho * (T)D.g[0];
-  Fy += rho * (T)D.g[1];
-  const T irho = T(1) / rho;
+  Fx += rho * K.g0;
+  Fy += rho * K.g1;
+  const T irho = rcp(rho);
   ux = (jx + T(0.5) * Fx) * irho;
   uy = (jy + T(0.5) * Fy) * irho;
-  const T tau = T(0.5) + T(3) / (r0 / (T)D.nu[0] + r1 / (T)D.nu[1] + r2 / (T)D.nu[2]);
-  const T s1 = T(1) / tau;
-  const T s4 = T(8) * (T(2) - s1) / (T(8) - s1);
+  // s1 = 1 / tau with tau = 1/2 + 3 / sum_k rho_k / mu_k
+  const T sum = r0 * K.inu[0] + r1 * K.inu[1] + r2 * K.inu[2];
+  const T s1 = sum * rcp(T(0.5) * sum + T(3));
+  const T s4 = T(8) * (T(2) - s1) * rcp(T(8) - s1);
   const T ruu = rho * (ux * ux + uy * uy);
   const T uF = ux * Fx + uy * Fy;
   const T h1 = T(1) - T(0.5) * s1, h4 = T(1) - T(0.5) * s4;
@@ -298,14 +335,14 @@ __device__ __forceinline__ void collide_shifted(const T f[9], T &Fx, T &Fy, T r0
 // Eq. (13)-(15): R_k = sum_{l != k} beta_kl (rho_k rho_l / rho) n_kl for k = 1, 2
 // (R_3 = -R_1 - R_2); out = (R_1x, R_1y, R_2x, R_2y).
 template <typename T>
-__device__ __forceinline__ void recolour_R(T r0, T r1, T r2, T rt, const T nrm[6], const DomainDev &D, T out[4]) {
-  const T irt = T(1) / rt;
+__device__ __forceinline__ void recolour_R(T r0, T r1, T r2, T rt, const T nrm[6], const KT<T> &K, T out[4]) {
+  const T irt = rcp(rt);
   T r3 = T(35) * r0 * r1 * r2 * irt * irt * irt;
   r3 = fmin(fmax(r3, T(0)), T(1));
-  const T b0 = (T)D.beta0;
-  const T b12 = b0 + b0 * r3 * (T)D.gX[0];
-  const T b13 = b0 + b0 * r3 * (T)D.gX[1];
-  const T b23 = b0 + b0 * r3 * (T)D.gX[2];
+  const T b0 = K.b0;
+  const T b12 = b0 + b0 * r3 * K.gX[0];
+  const T b13 = b0 + b0 * r3 * K.gX[1];
+  const T b23 = b0 + b0 * r3 * K.gX[2];
   const T a12 = b12 * r0 * r1 * irt, a13 = b13 * r0 * r2 * irt, a23 = b23 * r1 * r2 * irt;
   out[0] = a12 * nrm[0] + a13 * nrm[2];
   out[1] = a12 * nrm[1] + a13 * nrm[3];
@@ -342,7 +379,7 @@ __device__ __forceinline__ void fluid_parts(const Acc &acc, int dx, int dy, int 
 // Zou-He columns.  Produces the shifted total distribution and the three partial densities.
 template <typename T, class Acc>
 __device__ __forceinline__ void stream_node(const Acc &acc, int gx, uint8_t fl, int64_t li, const DomainDev &D,
-                                            const IbbNode *ibb, T fo[9], T &ra, T &rb, T &rc) {
+                                            const KT<T> &K, const IbbNode *ibb, T fo[9], T &ra, T &rb, T &rc) {
   ra = rb = rc = T(0);
   const IbbNode *ib = ((fl & FL_CURVED) && D.n_ibb > 0) ? find_ibb(ibb, D, li) : nullptr;
 #pragma unroll
@@ -382,7 +419,7 @@ __device__ __forceinline__ void stream_node(const Acc &acc, int gx, uint8_t fl, 
       } else {
         T own_a[3];
         fluid_parts<T>(acc, 0, 0, a, own_a);
-        const T c1 = T(1) / (T(2) * qd), c2 = T(1) - c1;
+        const T c1 = rcp(T(2) * qd), c2 = T(1) - c1;
         fo[a] = c1 * fab + c2 * acc.f(a, 0, 0);
         ra += c1 * own_ab[0] + c2 * own_a[0];
         rb += c1 * own_ab[1] + c2 * own_a[1];
@@ -396,7 +433,7 @@ __device__ __forceinline__ void stream_node(const Acc &acc, int gx, uint8_t fl, 
 #pragma unroll
     for (int a = 0; a < 9; ++a) ft[a] = fo[a] + wgt<T>(a);
     if (gx == 0) {
-      const T u = (T)D.u_in;
+      const T u = K.u_in;
       const T rw = (ft[0] + ft[2] + ft[4] + T(2) * (ft[3] + ft[6] + ft[7])) / (T(1) - u);
       ft[1] = ft[3] + T(2.0 / 3.0) * rw * u;
       ft[5] = ft[7] - T(0.5) * (ft[2] - ft[4]) + rw * u / T(6);
@@ -406,7 +443,7 @@ __device__ __forceinline__ void stream_node(const Acc &acc, int gx, uint8_t fl, 
       fo[5] = ft[5] - wgt<T>(5);
       fo[8] = ft[8] - wgt<T>(8);
     } else {
-      const T ro = (T)D.rho_out;
+      const T ro = K.rho_out;
       const T ux = -T(1) + (ft[0] + ft[2] + ft[4] + T(2) * (ft[1] + ft[5] + ft[8])) / ro;
       ft[3] = ft[1] - T(2.0 / 3.0) * ro * ux;
       ft[7] = ft[5] + T(0.5) * (ft[2] - ft[4]) - ro * ux / T(6);
@@ -452,10 +489,10 @@ __host__ __device__ inline size_t smem_bytes(int TX, int TY) {
   return (4 * n3 + 3 * n2 + 19 * n1) * sizeof(T) + ((n3 + 15) & ~(size_t)15);
 }
 
-template <typename T>
+template <typename T, int W1, int W3, int N1>
 struct TileAcc {
   const Smem<T> &L;
-  int p1, p3, W1, W3, N1;
+  int p1, p3;
   __device__ bool solid(int dx, int dy) const { return L.FL[p3 + dx + dy * W3] & FL_SOLID; }
   __device__ T f(int dir, int dx, int dy) const { return L.PF[dir * N1 + p1 + dx + dy * W1]; }
   __device__ T R(int c, int dx, int dy) const { return L.PR[c * N1 + p1 + dx + dy * W1]; }
@@ -465,13 +502,12 @@ struct TileAcc {
   }
 };
 
-template <typename S, typename T, bool FIELDS>
+template <typename S, typename T, bool FIELDS, int TX, int TY>
 __global__ __launch_bounds__(kThreads) void step_fused(StepArgs<S, T> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int TX = A.tile_x, TY = A.tile_y;
-  const int W3 = TX + 6, H3 = TY + 6, N3 = W3 * H3;
-  const int W2 = TX + 4, H2 = TY + 4, N2 = W2 * H2;
-  const int W1 = TX + 2, H1 = TY + 2, N1 = W1 * H1;
+  constexpr int W3 = TX + 6, H3 = TY + 6, N3 = W3 * H3;
+  constexpr int W2 = TX + 4, H2 = TY + 4, N2 = W2 * H2;
+  constexpr int W1 = TX + 2, H1 = TY + 2, N1 = W1 * H1;
   Smem<T> L;
   {
     T *p = reinterpret_cast<T *>(smem_raw);
@@ -493,6 +529,7 @@ __global__ __launch_bounds__(kThreads) void step_fused(StepArgs<S, T> A) {
     const T *Rin = A.rin + 3 * D.base;
     const S *Fin = A.fin + 9 * D.base;
     const int64_t P = D.plane;
+    const KT<T> K = make_kt<T>(D);
 
     // Phase A: C_k and rho on tile + 3 rings (with the wetting fill at the fill nodes).
     for (int q = tid; q < N3; q += kThreads) {
@@ -522,7 +559,7 @@ __global__ __launch_bounds__(kThreads) void step_fused(StepArgs<S, T> A) {
       }
       const T cc[3] = {L.C0[p3], L.C1[p3], L.C2[p3]};
       T txx, txy, tyy, nrm[6];
-      pair_stress(cc, g, L.RH[p3], D, eps_g, txx, txy, tyy, nrm);
+      pair_stress(cc, g, L.RH[p3], K, eps_g, txx, txy, tyy, nrm);
       L.Txx[q] = txx; L.Txy[q] = txy; L.Tyy[q] = tyy;
       if (lx >= 1 && lx <= W2 - 2 && ly >= 1 && ly <= H2 - 2) {
         const int p1 = (lx - 1) + (ly - 1) * W1;
@@ -562,7 +599,7 @@ __global__ __launch_bounds__(kThreads) void step_fused(StepArgs<S, T> A) {
       }
       const T r0 = L.C0[p3] * L.RH[p3], r1 = L.C1[p3] * L.RH[p3], r2 = L.C2[p3] * L.RH[p3];
       T fd[9], ux, uy;
-      collide_shifted(f, Fx, Fy, r0, r1, r2, D, fd, ux, uy);
+      collide_shifted(f, Fx, Fy, r0, r1, r2, K, fd, ux, uy);
       if (FIELDS) {
         const int64_t o = (int64_t)gy * D.nx + gx;
         const int64_t n = (int64_t)D.nx * D.ny;
@@ -575,7 +612,7 @@ __global__ __launch_bounds__(kThreads) void step_fused(StepArgs<S, T> A) {
       T nrm[6], Rv[4];
 #pragma unroll
       for (int c = 0; c < 6; ++c) nrm[c] = L.N[c * N1 + q];
-      recolour_R(r0, r1, r2, L.RH[p3], nrm, D, Rv);
+      recolour_R(r0, r1, r2, L.RH[p3], nrm, K, Rv);
 #pragma unroll
       for (int c = 0; c < 4; ++c) L.PR[c * N1 + q] = Rv[c];
     };
@@ -617,9 +654,9 @@ __global__ __launch_bounds__(kThreads) void step_fused(StepArgs<S, T> A) {
       const int p3 = (lx + 3) + (ly + 3) * W3;
       const uint8_t fl = L.FL[p3];
       if (fl & FL_SOLID) continue;  // solid slots keep their constant contents
-      TileAcc<T> acc{L, p1, p3, W1, W3, N1};
+      TileAcc<T, W1, W3, N1> acc{L, p1, p3};
       T fo[9], ra, rb, rc;
-      stream_node<T>(acc, gx, fl, li, D, A.ibb, fo, ra, rb, rc);
+      stream_node<T>(acc, gx, fl, li, D, K, A.ibb, fo, ra, rb, rc);
 #pragma unroll
       for (int a = 0; a < 9; ++a) store_s<S, T>(Fout + a * P + li, fo[a]);
       Rout[li] = ra;
@@ -678,6 +715,7 @@ __global__ __launch_bounds__(NT) void step_strip(StepArgs<S, T> A) {
     T *Rout = A.rout + 3 * D.base;
     S *Fout = A.fout + 9 * D.base;
     const int64_t P = D.plane;
+    const KT<T> K = make_kt<T>(D);
     const int gx = x0 - 3 + c;
     const int gxm = D.bcx == BCX_ZOUHE ? min(max(gx, 0), D.nx - 1) : wrap_small(gx, D.nx);
     const int yend = min(y1, D.ny);
@@ -709,7 +747,7 @@ __global__ __launch_bounds__(NT) void step_strip(StepArgs<S, T> A) {
         const T *mi = Cr + s0 * 4 * NT + c;
         const T cc[3] = {mi[0], mi[NT], mi[2 * NT]};
         T txx, txy, tyy, nrm[6];
-        pair_stress(cc, g, mi[3 * NT], D, eps_g, txx, txy, tyy, nrm);
+        pair_stress(cc, g, mi[3 * NT], K, eps_g, txx, txy, tyy, nrm);
         T *tr = Tr + mod_pos(r - 1, 3) * 3 * NT;
         tr[c] = txx; tr[NT + c] = txy; tr[2 * NT + c] = tyy;
       }
@@ -746,7 +784,7 @@ __global__ __launch_bounds__(NT) void step_strip(StepArgs<S, T> A) {
           const T cc[3] = {mi[0], mi[NT], mi[2 * NT]};
           const T rt = mi[3 * NT];
           T txx, txy, tyy, nrm[6];
-          pair_stress(cc, g, rt, D, eps_g, txx, txy, tyy, nrm);
+          pair_stress(cc, g, rt, K, eps_g, txx, txy, tyy, nrm);
           const int gy = D.yper ? wrap_small(yc, D.ny) : yc;
           const int64_t li = plane_index(gxm, gy, D.pitch);
           T f[9];
@@ -754,8 +792,8 @@ __global__ __launch_bounds__(NT) void step_strip(StepArgs<S, T> A) {
           for (int a = 0; a < 9; ++a) f[a] = load_s<S, T>(Fin + a * P + li);
           const T r0 = cc[0] * rt, r1 = cc[1] * rt, r2 = cc[2] * rt;
           T fd[9], ux, uy, Rv[4];
-          collide_shifted(f, Fx, Fy, r0, r1, r2, D, fd, ux, uy);
-          recolour_R(r0, r1, r2, rt, nrm, D, Rv);
+          collide_shifted(f, Fx, Fy, r0, r1, r2, K, fd, ux, uy);
+          recolour_R(r0, r1, r2, rt, nrm, K, Rv);
           T *pr = Pr + mod_pos(yc, 3) * 13 * NT + c;
 #pragma unroll
           for (int a = 0; a < 9; ++a) pr[a * NT] = fd[a];
@@ -777,7 +815,7 @@ __global__ __launch_bounds__(NT) void step_strip(StepArgs<S, T> A) {
           acc.cs[0] = mod_pos(yd - 1, 6); acc.cs[1] = s0; acc.cs[2] = mod_pos(yd + 1, 6);
           acc.ps[0] = mod_pos(yd - 1, 3); acc.ps[1] = mod_pos(yd, 3); acc.ps[2] = mod_pos(yd + 1, 3);
           T fo[9], ra, rb, rc;
-          stream_node<T>(acc, x, fl, li, D, A.ibb, fo, ra, rb, rc);
+          stream_node<T>(acc, x, fl, li, D, K, A.ibb, fo, ra, rb, rc);
 #pragma unroll
           for (int a = 0; a < 9; ++a) store_s<S, T>(Fout + a * P + li, fo[a]);
           Rout[li] = ra;
@@ -843,12 +881,29 @@ hipError_t launch_fill(const FillArgs<T> &a, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Tile shapes compiled into the tile kernel (LDS neighbour offsets become immediates).
+#define LBM3_TILE_SHAPES(X) X(32, 8) X(16, 16) X(64, 4) X(64, 8)
+
+bool tile_supported(int tx, int ty) {
+#define LBM3_TS(a, b) if (tx == a && ty == b) return true;
+  LBM3_TILE_SHAPES(LBM3_TS)
+#undef LBM3_TS
+  return false;
+}
+
 template <typename S, typename T>
 hipError_t launch_step(const StepArgs<S, T> &a, int grid, int mode, bool fields, hipStream_t s) {
-  if (fields) {
-    hipLaunchKernelGGL((step_fused<S, T, true>), dim3(grid), dim3(kThreads), smem_bytes<T>(a.tile_x, a.tile_y), s, a);
-  } else if (mode == MODE_TILE) {
-    hipLaunchKernelGGL((step_fused<S, T, false>), dim3(grid), dim3(kThreads), smem_bytes<T>(a.tile_x, a.tile_y), s, a);
+  if (fields || mode == MODE_TILE) {
+    const size_t sm = smem_bytes<T>(a.tile_x, a.tile_y);
+#define LBM3_TL(X, Y)                                                                              \
+    if (a.tile_x == X && a.tile_y == Y) {                                                          \
+      if (fields) hipLaunchKernelGGL((step_fused<S, T, true, X, Y>), dim3(grid), dim3(kThreads), sm, s, a); \
+      else hipLaunchKernelGGL((step_fused<S, T, false, X, Y>), dim3(grid), dim3(kThreads), sm, s, a);       \
+      return hipGetLastError();                                                                    \
+    }
+    LBM3_TILE_SHAPES(LBM3_TL)
+#undef LBM3_TL
+    return hipErrorInvalidValue;
   } else if (mode == MODE_STRIP128) {
     hipLaunchKernelGGL((step_strip<S, T, 128>), dim3(grid), dim3(128), strip_smem_bytes<T>(128), s, a);
   } else {
@@ -861,17 +916,17 @@ hipError_t launch_step(const StepArgs<S, T> &a, int grid, int mode, bool fields,
 hipError_t init_kernel_attributes() {
   const int lim = 160 * 1024;
   hipError_t e = hipSuccess, r;
-#define LBM3_ATTR(S, T, F)                                                                    \
-  r = hipFuncSetAttribute((const void *)step_fused<S, T, F>,                                  \
+#define LBM3_ATTR1(S, T, F, X, Y)                                                           \
+  r = hipFuncSetAttribute((const void *)step_fused<S, T, F, X, Y>,                            \
                           hipFuncAttributeMaxDynamicSharedMemorySize, lim);                   \
   if (r != hipSuccess) e = r;
-  LBM3_ATTR(double, double, false)
-  LBM3_ATTR(double, double, true)
-  LBM3_ATTR(float, float, false)
-  LBM3_ATTR(float, float, true)
-  LBM3_ATTR(__half, float, false)
-  LBM3_ATTR(__half, float, true)
-#undef LBM3_ATTR
+#define LBM3_ATTRT(X, Y)                                                                      \
+  LBM3_ATTR1(double, double, false, X, Y) LBM3_ATTR1(double, double, true, X, Y)              \
+  LBM3_ATTR1(float, float, false, X, Y) LBM3_ATTR1(float, float, true, X, Y)                  \
+  LBM3_ATTR1(__half, float, false, X, Y) LBM3_ATTR1(__half, float, true, X, Y)
+  LBM3_TILE_SHAPES(LBM3_ATTRT)
+#undef LBM3_ATTRT
+#undef LBM3_ATTR1
 #define LBM3_ATTR2(S, T, N)                                                                   \
   r = hipFuncSetAttribute((const void *)step_strip<S, T, N>,                                  \
                           hipFuncAttributeMaxDynamicSharedMemorySize, lim);                   \
