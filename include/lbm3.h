@@ -102,6 +102,8 @@ typedef struct {
                                 segment (0 = default), tile_x unused */
   int32_t persistent_blocks; /* > 0: the fused kernel runs this many work-groups that loop over
                                 the (domain, tile) work list; 0: one work-group per work item */
+  int32_t adjoint;           /* 1: also lay out the scratch of the adjoint step (lbm3_adjoint_*);
+                                LBM3_F64 and LBM3_F32 only; 0: forward only */
 } lbm3_options;
 
 /* Bytes of device workspace lbm3_create needs for n domains (d[0..n-1]) and these options. */
@@ -142,6 +144,39 @@ lbm3_status lbm3_mass(lbm3_ctx *c, double *host_out);
 lbm3_status lbm3_state_bytes(const lbm3_ctx *c, size_t *bytes);
 lbm3_status lbm3_get_state(lbm3_ctx *c, void *dev_dst);
 lbm3_status lbm3_set_state(lbm3_ctx *c, const void *dev_src);
+
+/* Changes the wetting and tension parameters of domain `domain` (theta_deg[2] = theta13,
+ * theta23 in degrees; sigma[3] = sigma12, sigma13, sigma23) with the checks of lbm3_create:
+ * Eq. (18) fixes theta12 and Eq. (15) the factors g(X_kl).  The state is kept.  Synchronises. */
+lbm3_status lbm3_set_params(lbm3_ctx *c, int32_t domain, const double *theta_deg, const double *sigma);
+
+/* ---- Adjoint (reverse-mode derivative) of the time step --------------------------------------
+ * For a loss L of the partial densities after T steps, the adjoint state lambda_t = dL/ds_t
+ * (s_t = the state at step t: shifted distributions and partial densities at fluid nodes) obeys
+ * lambda_t = (ds_{t+1}/ds_t)^T lambda_{t+1}; the parameter gradient sums
+ * (ds_{t+1}/dp)^T lambda_{t+1} over the steps.  The derivative is that of the discrete update
+ * as implemented (Eq. 1-22; at the non-smooth points -- the max/min of Eq. 22, clamps, the
+ * |G| threshold of the normals -- the branch the forward took).  Needs a context created with
+ * options.adjoint = 1.  lambda buffers are device buffers of lbm3_state_bytes in the state
+ * layout and compute type; entries at solid nodes are zero.
+ *
+ * lbm3_adjoint_seed starts a backward pass: clears the parameter-gradient accumulators and
+ * writes lambda_T = dL/drho_k into dev_lambda (distribution part zero).  dev_grad_rho: device,
+ * FP64, the domains' [3][ny][nx] arrays concatenated in domain order; values at solid nodes are
+ * ignored.  Asynchronous. */
+lbm3_status lbm3_adjoint_seed(lbm3_ctx *c, const double *dev_grad_rho, void *dev_lambda);
+
+/* One step back: from the forward state s_t (dev_state, as written by lbm3_get_state) and
+ * lambda_{t+1} (dev_lambda_in) writes lambda_t (dev_lambda_out, a different buffer) and adds
+ * step t's parameter partials to the accumulators.  Leaves the context's own state alone.
+ * Asynchronous. */
+lbm3_status lbm3_adjoint_step(lbm3_ctx *c, const void *dev_state, const void *dev_lambda_in,
+                              void *dev_lambda_out);
+
+/* The accumulated gradient dL/dp per domain: host_grad[5*n] = (theta13 [per degree], theta23
+ * [per degree], sigma12, sigma13, sigma23), the chain rule through theta12 (Eq. 18) and g(X_kl)
+ * (Eq. 15) included.  Synchronises. */
+lbm3_status lbm3_adjoint_grad(lbm3_ctx *c, double *host_grad);
 
 /* Average device time (ms) of one launch of the wetting-fill kernel and of the fused step kernel
  * over nsteps plain steps, from HIP events recorded on the context's stream around each launch.

@@ -7,8 +7,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbm3.so")
-SOURCES = [os.path.join(CSRC, f) for f in ("lbm3_kernels.hip", "lbm3_api.cpp")]
-HEADERS = [os.path.join(CSRC, f) for f in ("lbm3_internal.h", "lbm3_kernels.h")] + [
+SOURCES = [os.path.join(CSRC, f) for f in ("lbm3_kernels.hip", "lbm3_adjoint.hip", "lbm3_api.cpp")]
+HEADERS = [os.path.join(CSRC, f) for f in ("lbm3_internal.h", "lbm3_kernels.h", "lbm3_device.h", "lbm3_adjoint.h")] + [
     os.path.join(ROOT, "include", "lbm3.h")]
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -1,0 +1,63 @@
+// lbm3_adjoint.h -- argument block and launcher of the adjoint step (internal to liblbm3).
+//
+// The adjoint works on an extended grid per domain: columns -1..nx (the two outer columns are
+// the zero-gradient ghost columns of a Zou-He x boundary) and rows -2..ny+1 (the off-grid solid
+// rows of a non-periodic y boundary); element (i, j) of a domain's extended plane is
+// abase + (i + 1) + (nx + 2) (j + 2).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lbm3_internal.h"
+
+namespace lbm3 {
+
+// Planes of the adjoint scratch (each of total_aplane elements of type T).
+enum {
+  AX_C = 0,      // 4: C_k, rho of the forward state
+  AX_T = 4,      // 3: stress
+  AX_N = 7,      // 6: pair normals
+  AX_F = 13,     // 2: interfacial force
+  AX_P = 15,     // 13: post-collision shifted f (9), R (4)
+  AL_P = 28,     // 13: adjoint of the post-collision data
+  AL_F = 41,     // 2: adjoint of F
+  AL_N = 43,     // 6: adjoint of n
+  AL_T = 49,     // 3: adjoint of the stress
+  AL_G = 52,     // 6: adjoint of the colour gradients
+  AL_C = 58,     // 4: adjoint of C_k and rho
+  A_PLANES = 62
+};
+
+template <typename S, typename T>
+struct AdjArgs {
+  const DomainDev *doms;
+  const WorkItem *work;  // tiles of 32 x 8 over each domain's extended range
+  int n_work;
+  const uint8_t *flags;
+  const IbbNode *ibb;
+  const FillNode *fill;
+  int n_fill;
+  const T *fillC;
+  const S *fin;     // forward state at t: distributions
+  const T *rin;     //                      densities
+  T *X;             // adjoint scratch, A_PLANES planes
+  int64_t aplane;   // elements per scratch plane (sum over domains)
+  const T *lin;     // adjoint of the state at t+1 (copy), 12 planes in the state layout
+  T *lout;          // adjoint of the state at t, 12 planes in the state layout
+  double *raw;      // [9 n_dom] raw parameter partials
+  T eps_g;
+};
+
+// The adjoint of one step (every kernel, in order).  tplane = elements of one state plane summed
+// over the domains (the offset of the density planes in the state layout, over 9).
+template <typename S, typename T>
+hipError_t launch_adjoint(const AdjArgs<S, T> &a, int64_t tplane, hipStream_t s);
+
+// Writes dL/drho_k from g (flat [3][ny][nx] per domain) into the density planes of lam at fluid
+// nodes; work = 32 x 8 tiles over the real nodes.
+template <typename T>
+hipError_t launch_adjoint_seed(const DomainDev *doms, const WorkItem *work, int n_work, const uint8_t *flags,
+                               const double *g, T *lam, int64_t tplane, hipStream_t s);
+
+}  // namespace lbm3

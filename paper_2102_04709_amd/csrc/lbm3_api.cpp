@@ -22,6 +22,7 @@
 #include <vector>
 
 #include "lbm3.h"
+#include "lbm3_adjoint.h"
 #include "lbm3_internal.h"
 #include "lbm3_kernels.h"
 
@@ -43,6 +44,7 @@ const Candidate kCands[] = {{MODE_TILE, 32, 8},     {MODE_TILE, 16, 16},    {MOD
 const int kMinTileArea = 256;
 const int kMinStripRows = 8;
 const int kFieldTileX = 32, kFieldTileY = 8;  // tile of the field export
+const int kAdjTileX = 32, kAdjTileY = 8;      // tile of the adjoint kernels
 
 int round_up(int v, int m) { return (v + m - 1) / m * m; }
 
@@ -55,9 +57,10 @@ struct DomHost {
 
 struct Layout {
   size_t off_F[2], off_R[2], off_flags, off_fill, off_fillC, off_ibb, off_doms, off_work, off_fwork, off_partial,
-      off_chunk_dom, off_chunk_first, off_mass, off_bad, total;
+      off_chunk_dom, off_chunk_first, off_mass, off_bad, off_aX, off_awork, off_raw, total;
   int64_t total_plane;
-  int n_fill, n_ibb, n_chunks, max_work, n_fwork;
+  int64_t aplane;  // elements of one adjoint scratch plane (all domains' extended grids)
+  int n_fill, n_ibb, n_chunks, max_work, n_fwork, n_awork;
 };
 
 size_t s_size(int precision) { return precision == LBM3_F64 ? 8 : (precision == LBM3_F32 ? 4 : 2); }
@@ -68,6 +71,74 @@ double g_of_X(double X) {
   if (X < 0.0) return 1.0 - std::sqrt(1.0 - X * X);
   if (X <= 1.0) return std::sqrt(1.0 - X * X) - 1.0;
   return -1.0;
+}
+
+// X_kl of Eq. (15) for the pair whose own tension is c, the other two being a and b:
+// X = (a^2 + b^2 - c^2) / (2ab), with its partials.
+double pair_X(double c, double a, double b, double *dc = nullptr, double *da = nullptr, double *db = nullptr) {
+  if (dc) *dc = -c / (a * b);
+  if (da) *da = (a * a - b * b + c * c) / (2.0 * a * a * b);
+  if (db) *db = (b * b - a * a + c * c) / (2.0 * a * b * b);
+  return (a * a + b * b - c * c) / (2.0 * a * b);
+}
+
+double g_of_X_prime(double X) {
+  if (X <= -1.0 || X >= 1.0) return 0.0;
+  const double r = std::sqrt(1.0 - X * X);
+  return X < 0.0 ? X / r : -X / r;
+}
+
+// The parameters a domain derives from (theta13, theta23) and the tensions: theta12 by Eq. (18)
+// (with theta31 = pi - theta13) and g(X_kl) of Eq. (15).  Returns an error message or null.
+const char *derive_params(const double *theta_deg, const double *sigma, DomainDev &D) {
+  for (int k = 0; k < 3; ++k)
+    if (!(sigma[k] > 0.0)) return "every interfacial tension must be > 0";
+  for (int k = 0; k < 2; ++k)
+    if (!(theta_deg[k] > 0.0 && theta_deg[k] < 180.0)) return "contact angles must lie in (0, 180) degrees";
+  const double th13 = theta_deg[0] * kPI / 180.0, th23 = theta_deg[1] * kPI / 180.0;
+  double c12 = (sigma[1] * std::cos(th13) - sigma[2] * std::cos(th23)) / sigma[0];
+  if (std::fabs(c12) > 1.0 + 1e-12) return "contact angles and tensions violate Eq. (18): |cos theta12| > 1";
+  c12 = std::min(1.0, std::max(-1.0, c12));
+  const double s12 = sigma[0], s13 = sigma[1], s23 = sigma[2];
+  for (int k = 0; k < 3; ++k) D.sig[k] = sigma[k];
+  D.gX[0] = g_of_X(pair_X(s12, s13, s23));
+  D.gX[1] = g_of_X(pair_X(s13, s12, s23));
+  D.gX[2] = g_of_X(pair_X(s23, s12, s13));
+  D.th13 = th13;
+  D.th23 = th23;
+  D.th12 = std::acos(c12);
+  return nullptr;
+}
+
+// J[r][p]: derivative of the raw parameter r of the adjoint kernels (sigma12, sigma13, sigma23,
+// g(X_12), g(X_13), g(X_23), theta13, theta23, theta12 in radians) with respect to the public
+// parameter p (theta13, theta23 in degrees, sigma12, sigma13, sigma23).
+void param_jacobian(const double *theta_deg, const double *sigma, double J[9][5]) {
+  for (int r = 0; r < 9; ++r)
+    for (int p = 0; p < 5; ++p) J[r][p] = 0.0;
+  const double deg = kPI / 180.0;
+  for (int k = 0; k < 3; ++k) J[k][2 + k] = 1.0;
+  const double s12 = sigma[0], s13 = sigma[1], s23 = sigma[2];
+  double dc, da, db;
+  // pair 12: own s12, others s13, s23
+  double X = pair_X(s12, s13, s23, &dc, &da, &db), g = g_of_X_prime(X);
+  J[3][2] = g * dc; J[3][3] = g * da; J[3][4] = g * db;
+  X = pair_X(s13, s12, s23, &dc, &da, &db); g = g_of_X_prime(X);
+  J[4][3] = g * dc; J[4][2] = g * da; J[4][4] = g * db;
+  X = pair_X(s23, s12, s13, &dc, &da, &db); g = g_of_X_prime(X);
+  J[5][4] = g * dc; J[5][2] = g * da; J[5][3] = g * db;
+  J[6][0] = deg;
+  J[7][1] = deg;
+  const double th13 = theta_deg[0] * deg, th23 = theta_deg[1] * deg;
+  const double c12 = (s13 * std::cos(th13) - s23 * std::cos(th23)) / s12;
+  if (std::fabs(c12) < 1.0) {
+    const double dth = -1.0 / std::sqrt(1.0 - c12 * c12);  // d theta12 / d cos theta12
+    J[8][0] = dth * (-s13 * std::sin(th13) / s12) * deg;
+    J[8][1] = dth * (s23 * std::sin(th23) / s12) * deg;
+    J[8][2] = dth * (-c12 / s12);
+    J[8][3] = dth * (std::cos(th13) / s12);
+    J[8][4] = dth * (-std::cos(th23) / s12);
+  }
 }
 
 bool validate_and_build(const lbm3_domain &d, int dom, double beta0, DomHost &H, std::string &err) {
@@ -90,13 +161,11 @@ bool validate_and_build(const lbm3_domain &d, int dom, double beta0, DomHost &H,
     const double tau = 0.5 + 3.0 * d.nu[k];
     if (!(tau > 0.5 && tau <= 10.0)) return fail("viscosity gives tau outside (0.5, 10]");
   }
-  for (int k = 0; k < 2; ++k)
-    if (!(d.theta_deg[k] > 0.0 && d.theta_deg[k] < 180.0)) return fail("contact angles must lie in (0, 180) degrees");
-  const double th13 = d.theta_deg[0] * kPI / 180.0, th23 = d.theta_deg[1] * kPI / 180.0;
-  // Eq. (18) with theta31 = pi - theta13.
-  double c12 = (d.sigma[1] * std::cos(th13) - d.sigma[2] * std::cos(th23)) / d.sigma[0];
-  if (std::fabs(c12) > 1.0 + 1e-12) return fail("contact angles and tensions violate Eq. (18): |cos theta12| > 1");
-  c12 = std::min(1.0, std::max(-1.0, c12));
+  {
+    DomainDev tmp;
+    const char *m = derive_params(d.theta_deg, d.sigma, tmp);
+    if (m) return fail(m);
+  }
   const int nx = d.nx, ny = d.ny;
   const int pitch = round_up(nx, 64);
   const int rows = ny + 4;
@@ -110,20 +179,9 @@ bool validate_and_build(const lbm3_domain &d, int dom, double beta0, DomHost &H,
   D.plane = (int64_t)pitch * rows;
   D.u_in = d.u_in;
   D.rho_out = d.rho_out;
-  for (int k = 0; k < 3; ++k) {
-    D.nu[k] = d.nu[k];
-    D.sig[k] = d.sigma[k];
-  }
-  {  // X_kl of Eq. (15) for pairs 12, 13, 23 (m is the third fluid)
-    const double s12 = d.sigma[0], s13 = d.sigma[1], s23 = d.sigma[2];
-    D.gX[0] = g_of_X((s13 * s13 + s23 * s23 - s12 * s12) / (2.0 * s13 * s23));
-    D.gX[1] = g_of_X((s12 * s12 + s23 * s23 - s13 * s13) / (2.0 * s12 * s23));
-    D.gX[2] = g_of_X((s12 * s12 + s13 * s13 - s23 * s23) / (2.0 * s12 * s13));
-  }
+  for (int k = 0; k < 3; ++k) D.nu[k] = d.nu[k];
+  (void)derive_params(d.theta_deg, d.sigma, D);
   D.beta0 = beta0;
-  D.th13 = th13;
-  D.th23 = th23;
-  D.th12 = std::acos(c12);
   D.g[0] = d.body_force[0];
   D.g[1] = d.body_force[1];
 
@@ -305,11 +363,18 @@ bool plan(const lbm3_domain *d, int n, const lbm3_options *o, std::vector<DomHos
   H.assign(n, DomHost());
   for (int i = 0; i < n; ++i)
     if (!validate_and_build(d[i], i, beta0, H[i], err)) return false;
-  int64_t base = 0;
-  int nf = 0, ni = 0, nch = 0, maxw = 0, nfw = 0;
+  if (o->adjoint != 0 && o->adjoint != 1) return err = "adjoint must be 0 or 1", false;
+  if (o->adjoint && o->precision == LBM3_F32_STORE_F16) return err = "the adjoint needs LBM3_F64 or LBM3_F32", false;
+  int64_t base = 0, abase = 0, goff = 0;
+  int nf = 0, ni = 0, nch = 0, maxw = 0, nfw = 0, naw = 0;
   for (int i = 0; i < n; ++i) {
     H[i].dd.base = base;
     base += H[i].dd.plane;
+    H[i].dd.abase = abase;
+    abase += (int64_t)(d[i].nx + 2) * (d[i].ny + 4);
+    H[i].dd.goff = goff;
+    goff += 3 * (int64_t)d[i].nx * d[i].ny;
+    naw += tiles_of(d[i].nx + 2, d[i].ny + 4, kAdjTileX, kAdjTileY);
     H[i].dd.fill_off = nf;
     H[i].dd.n_fill = (int)H[i].fill.size();
     nf += H[i].dd.n_fill;
@@ -332,6 +397,8 @@ bool plan(const lbm3_domain *d, int n, const lbm3_options *o, std::vector<DomHos
   L.n_chunks = nch;
   L.max_work = maxw;
   L.n_fwork = nfw;
+  L.aplane = abase;
+  L.n_awork = o->adjoint ? naw : 0;
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t r = off;
@@ -354,6 +421,12 @@ bool plan(const lbm3_domain *d, int n, const lbm3_options *o, std::vector<DomHos
   L.off_chunk_first = take(sizeof(int) * (n + 1));
   L.off_mass = take(sizeof(double) * 3 * n);
   L.off_bad = take(sizeof(int));
+  L.off_aX = L.off_awork = L.off_raw = 0;
+  if (o->adjoint) {
+    L.off_aX = take((size_t)A_PLANES * (size_t)abase * t_size(prec));
+    L.off_awork = take(sizeof(WorkItem) * naw);
+    L.off_raw = take(sizeof(double) * 9 * n);
+  }
   L.total = off;
   return true;
 }
@@ -377,6 +450,12 @@ struct lbm3_ctx {
   std::vector<WorkItem> work;
   std::vector<WorkItem> fwork;  // tiles of the field export
   std::vector<int> fwork_off, fwork_n;
+  std::vector<WorkItem> awork;  // tiles of the adjoint over the extended grids
+  struct Params {
+    double theta_deg[2], sigma[3];
+  };
+  std::vector<Params> params;  // the public wetting/tension parameters of each domain
+  bool adjoint = false;
   hipGraphExec_t graph = nullptr;
   bool graph_valid = false;
   std::string err;
@@ -431,10 +510,26 @@ void build_work_for(lbm3_ctx *c, int mode, int tx, int ty, std::vector<WorkItem>
 // kernel with its own tile list (built once at creation).
 void build_work(lbm3_ctx *c) { build_work_for(c, c->mode, c->tx, c->ty, c->work, nullptr, nullptr); }
 
+// Tiles of the adjoint kernels over each domain's extended range: columns -1..nx with a Zou-He
+// x boundary (its ghost columns carry a stress), rows -2..ny+1 with a non-periodic y axis.
+void build_adjoint_work(lbm3_ctx *c) {
+  c->awork.clear();
+  for (int d = 0; d < c->n; ++d) {
+    const DomainDev &D = c->doms[d];
+    const int x0 = D.bcx == BCX_ZOUHE ? -1 : 0, x1 = D.bcx == BCX_ZOUHE ? D.nx + 1 : D.nx;
+    const int y0 = D.yper ? 0 : -2, y1 = D.yper ? D.ny : D.ny + 2;
+    for (int y = y0; y < y1; y += kAdjTileY)
+      for (int x = x0; x < x1; x += kAdjTileX)
+        c->awork.push_back(WorkItem{d, x, y, std::min(x + kAdjTileX, x1), std::min(y + kAdjTileY, y1), 0, 0, 0});
+  }
+}
+
 lbm3_status upload_tables(lbm3_ctx *c) {
   HIPC(c, hipMemcpyAsync(c->at<void>(c->L.off_doms), c->doms.data(), sizeof(DomainDev) * c->n, hipMemcpyHostToDevice, c->stream));
   HIPC(c, hipMemcpyAsync(c->at<void>(c->L.off_work), c->work.data(), sizeof(WorkItem) * c->work.size(), hipMemcpyHostToDevice, c->stream));
   HIPC(c, hipMemcpyAsync(c->at<void>(c->L.off_fwork), c->fwork.data(), sizeof(WorkItem) * c->fwork.size(), hipMemcpyHostToDevice, c->stream));
+  if (c->adjoint && !c->awork.empty())
+    HIPC(c, hipMemcpyAsync(c->at<void>(c->L.off_awork), c->awork.data(), sizeof(WorkItem) * c->awork.size(), hipMemcpyHostToDevice, c->stream));
   HIPC(c, hipStreamSynchronize(c->stream));
   return LBM3_OK;
 }
@@ -583,6 +678,38 @@ lbm3_status fields_t(lbm3_ctx *c, int dom, void *rho, void *u, void *force) {
   return LBM3_OK;
 }
 
+template <typename S, typename T>
+lbm3_status adjoint_step_t(lbm3_ctx *c, const void *state, const void *lin, void *lout) {
+  size_t bytes = 0;
+  (void)lbm3_state_bytes(c, &bytes);
+  HIPC(c, hipMemsetAsync(lout, 0, bytes, c->stream));
+  const size_t fb = 9 * (size_t)c->L.total_plane * sizeof(S);
+  const S *fin = reinterpret_cast<const S *>(state);
+  const T *rin = reinterpret_cast<const T *>(reinterpret_cast<const char *>(state) + fb);
+  FillArgs<T> f = fill_args<T>(c, 0);
+  f.rho = rin;
+  HIPC(c, launch_fill<T>(f, c->stream));
+  AdjArgs<S, T> a;
+  a.doms = c->at<DomainDev>(c->L.off_doms);
+  a.work = c->at<WorkItem>(c->L.off_awork);
+  a.n_work = (int)c->awork.size();
+  a.flags = c->at<uint8_t>(c->L.off_flags);
+  a.ibb = c->at<IbbNode>(c->L.off_ibb);
+  a.fill = c->at<FillNode>(c->L.off_fill);
+  a.n_fill = c->L.n_fill;
+  a.fillC = c->at<T>(c->L.off_fillC);
+  a.fin = fin;
+  a.rin = rin;
+  a.X = c->at<T>(c->L.off_aX);
+  a.aplane = c->L.aplane;
+  a.lin = reinterpret_cast<const T *>(lin);
+  a.lout = reinterpret_cast<T *>(lout);
+  a.raw = c->at<double>(c->L.off_raw);
+  a.eps_g = sizeof(T) == 8 ? T(1e-12) : T(1e-7);
+  HIPC(c, (launch_adjoint<S, T>(a, c->L.total_plane, c->stream)));
+  return LBM3_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -645,6 +772,10 @@ lbm3_status lbm3_create(const lbm3_domain *d, int32_t n, const lbm3_options *o, 
     c->ty = o->tile_y > 0 ? o->tile_y : 64;
   }
   for (auto &h : H) c->doms.push_back(h.dd);
+  for (int i = 0; i < n; ++i)
+    c->params.push_back({{d[i].theta_deg[0], d[i].theta_deg[1]}, {d[i].sigma[0], d[i].sigma[1], d[i].sigma[2]}});
+  c->adjoint = o->adjoint == 1;
+  if (c->adjoint) build_adjoint_work(c);
   auto bail = [&](lbm3_status s) {
     g_plan_err = c->err;
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
@@ -794,6 +925,90 @@ lbm3_status lbm3_set_state(lbm3_ctx *c, const void *dev_src) {
   const char *s = reinterpret_cast<const char *>(dev_src);
   HIPC(c, hipMemcpyAsync(c->at<void>(c->L.off_F[c->cur]), s, fb, hipMemcpyDeviceToDevice, c->stream));
   HIPC(c, hipMemcpyAsync(c->at<void>(c->L.off_R[c->cur]), s + fb, rb, hipMemcpyDeviceToDevice, c->stream));
+  return LBM3_OK;
+}
+
+lbm3_status lbm3_set_params(lbm3_ctx *c, int32_t domain, const double *theta_deg, const double *sigma) {
+  if (!c) return LBM3_EINVAL;
+  if (domain < 0 || domain >= c->n || !theta_deg || !sigma) {
+    c->err = "bad domain index or missing parameters";
+    return LBM3_EINVAL;
+  }
+  DomainDev D = c->doms[domain];
+  const char *m = derive_params(theta_deg, sigma, D);
+  if (m) {
+    c->err = m;
+    return LBM3_EINVAL;
+  }
+  c->doms[domain] = D;
+  c->params[domain] = {{theta_deg[0], theta_deg[1]}, {sigma[0], sigma[1], sigma[2]}};
+  HIPC(c, hipMemcpyAsync(c->at<DomainDev>(c->L.off_doms) + domain, &c->doms[domain], sizeof(DomainDev),
+                         hipMemcpyHostToDevice, c->stream));
+  HIPC(c, hipStreamSynchronize(c->stream));
+  return LBM3_OK;
+}
+
+static lbm3_status adjoint_ready(lbm3_ctx *c) {
+  if (!c) return LBM3_EINVAL;
+  if (!c->adjoint) {
+    c->err = "the context was created without options.adjoint = 1";
+    return LBM3_ESTATE;
+  }
+  return LBM3_OK;
+}
+
+lbm3_status lbm3_adjoint_seed(lbm3_ctx *c, const double *dev_grad_rho, void *dev_lambda) {
+  lbm3_status st = adjoint_ready(c);
+  if (st != LBM3_OK) return st;
+  if (!dev_grad_rho || !dev_lambda) {
+    c->err = "missing buffer";
+    return LBM3_EINVAL;
+  }
+  size_t bytes = 0;
+  (void)lbm3_state_bytes(c, &bytes);
+  HIPC(c, hipMemsetAsync(dev_lambda, 0, bytes, c->stream));
+  HIPC(c, hipMemsetAsync(c->at<void>(c->L.off_raw), 0, sizeof(double) * 9 * c->n, c->stream));
+  const DomainDev *doms = c->at<DomainDev>(c->L.off_doms);
+  const WorkItem *w = c->at<WorkItem>(c->L.off_fwork);
+  const uint8_t *fl = c->at<uint8_t>(c->L.off_flags);
+  const int nw = (int)c->fwork.size();
+  if (c->precision == LBM3_F64)
+    HIPC(c, launch_adjoint_seed<double>(doms, w, nw, fl, dev_grad_rho, reinterpret_cast<double *>(dev_lambda),
+                                        c->L.total_plane, c->stream));
+  else
+    HIPC(c, launch_adjoint_seed<float>(doms, w, nw, fl, dev_grad_rho, reinterpret_cast<float *>(dev_lambda),
+                                       c->L.total_plane, c->stream));
+  return LBM3_OK;
+}
+
+lbm3_status lbm3_adjoint_step(lbm3_ctx *c, const void *dev_state, const void *dev_lambda_in, void *dev_lambda_out) {
+  lbm3_status st = adjoint_ready(c);
+  if (st != LBM3_OK) return st;
+  if (!dev_state || !dev_lambda_in || !dev_lambda_out || dev_lambda_in == dev_lambda_out) {
+    c->err = "missing buffer, or lambda_in and lambda_out are the same buffer";
+    return LBM3_EINVAL;
+  }
+  if (c->precision == LBM3_F64) return adjoint_step_t<double, double>(c, dev_state, dev_lambda_in, dev_lambda_out);
+  return adjoint_step_t<float, float>(c, dev_state, dev_lambda_in, dev_lambda_out);
+}
+
+lbm3_status lbm3_adjoint_grad(lbm3_ctx *c, double *host_grad) {
+  lbm3_status st = adjoint_ready(c);
+  if (st != LBM3_OK) return st;
+  if (!host_grad) return LBM3_EINVAL;
+  std::vector<double> raw(9 * (size_t)c->n);
+  HIPC(c, hipMemcpyAsync(raw.data(), c->at<void>(c->L.off_raw), sizeof(double) * raw.size(), hipMemcpyDeviceToHost,
+                         c->stream));
+  HIPC(c, hipStreamSynchronize(c->stream));
+  for (int d = 0; d < c->n; ++d) {
+    double J[9][5];
+    param_jacobian(c->params[d].theta_deg, c->params[d].sigma, J);
+    for (int p = 0; p < 5; ++p) {
+      double g = 0.0;
+      for (int r = 0; r < 9; ++r) g += raw[9 * d + r] * J[r][p];
+      host_grad[5 * d + p] = g;
+    }
+  }
   return LBM3_OK;
 }
 

@@ -39,6 +39,8 @@ struct DomainDev {
   int32_t ibb_off, work_off, n_work, pad_;
   int64_t base;   // element offset of plane 0 of this domain (before the x9 / x3 factors)
   int64_t plane;  // P = pitch * (ny + 4)
+  int64_t abase;  // element offset of this domain in the adjoint's extended planes
+  int64_t goff;   // element offset of this domain in flat [3][ny][nx] field arrays
   double u_in, rho_out;
   double nu[3];
   double sig[3];   // sigma12, sigma13, sigma23

@@ -26,6 +26,7 @@ ABI_SYMBOLS = [
     "lbm3_workspace_bytes", "lbm3_create", "lbm3_step", "lbm3_fields", "lbm3_mass",
     "lbm3_state_bytes", "lbm3_get_state", "lbm3_set_state", "lbm3_kernel_times", "lbm3_autotune",
     "lbm3_query", "lbm3_last_error", "lbm3_plan_error", "lbm3_status_string", "lbm3_destroy",
+    "lbm3_set_params", "lbm3_adjoint_seed", "lbm3_adjoint_step", "lbm3_adjoint_grad",
 ]
 
 
@@ -45,7 +46,7 @@ class lbm3_options(C.Structure):
     _fields_ = [
         ("precision", C.c_int32), ("graph_block_steps", C.c_int32), ("beta0", C.c_double),
         ("kernel", C.c_int32), ("tile_x", C.c_int32), ("tile_y", C.c_int32),
-        ("persistent_blocks", C.c_int32),
+        ("persistent_blocks", C.c_int32), ("adjoint", C.c_int32),
     ]
 
 
@@ -86,6 +87,10 @@ def library() -> C.CDLL:
             "lbm3_plan_error": (C.c_char_p, []),
             "lbm3_status_string": (C.c_char_p, [i32]),
             "lbm3_destroy": (None, [vp]),
+            "lbm3_set_params": (i32, [vp, i32, dp, dp]),
+            "lbm3_adjoint_seed": (i32, [vp, vp, vp]),
+            "lbm3_adjoint_step": (i32, [vp, vp, vp, vp]),
+            "lbm3_adjoint_grad": (i32, [vp, dp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -123,7 +128,7 @@ class DomainArgs:
 
 
 def make_options(precision="f32", graph_block_steps=0, beta0=0.0, tile=None, persistent_blocks=0,
-                 kernel="tile"):
+                 kernel="tile", adjoint=False):
     o = lbm3_options()
     o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     o.graph_block_steps = int(graph_block_steps)
@@ -131,6 +136,7 @@ def make_options(precision="f32", graph_block_steps=0, beta0=0.0, tile=None, per
     o.kernel = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
     o.tile_x, o.tile_y = (0, 0) if tile is None else (int(tile[0]), int(tile[1]))
     o.persistent_blocks = int(persistent_blocks)
+    o.adjoint = 1 if adjoint else 0
     return o
 
 
@@ -208,13 +214,34 @@ def lbm3_destroy(ctx) -> None:
     library().lbm3_destroy(ctx)
 
 
+def lbm3_set_params(ctx, domain: int, theta_deg, sigma) -> None:
+    th = (C.c_double * 2)(*[float(v) for v in theta_deg])
+    sg = (C.c_double * 3)(*[float(v) for v in sigma])
+    _check(library().lbm3_set_params(ctx, int(domain), th, sg), ctx)
+
+
+def lbm3_adjoint_seed(ctx, grad_rho_ptr: int, lam_ptr: int) -> None:
+    _check(library().lbm3_adjoint_seed(ctx, C.c_void_p(grad_rho_ptr), C.c_void_p(lam_ptr)), ctx)
+
+
+def lbm3_adjoint_step(ctx, state_ptr: int, lam_in_ptr: int, lam_out_ptr: int) -> None:
+    _check(library().lbm3_adjoint_step(ctx, C.c_void_p(state_ptr), C.c_void_p(lam_in_ptr),
+                                       C.c_void_p(lam_out_ptr)), ctx)
+
+
+def lbm3_adjoint_grad(ctx, n_domains: int) -> np.ndarray:
+    out = np.zeros(5 * n_domains)
+    _check(library().lbm3_adjoint_grad(ctx, out.ctypes.data_as(C.POINTER(C.c_double))), ctx)
+    return out.reshape(n_domains, 5)
+
+
 # ---- convenience wrapper --------------------------------------------------------------------
 
 class Simulation:
     """Domains advanced together on one GPU by liblbm3."""
 
     def __init__(self, workloads, precision="f32", graph_block_steps=0, tile=None,
-                 persistent_blocks=0, beta0=0.0, device="cuda:0", kernel="tile"):
+                 persistent_blocks=0, beta0=0.0, device="cuda:0", kernel="tile", adjoint=False):
         import torch
 
         if not isinstance(workloads, (list, tuple)):
@@ -223,7 +250,8 @@ class Simulation:
         self.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         self.device = torch.device(device)
         self.domains = DomainArgs(self.workloads)
-        self.options = make_options(precision, graph_block_steps, beta0, tile, persistent_blocks, kernel)
+        self.options = make_options(precision, graph_block_steps, beta0, tile, persistent_blocks, kernel,
+                                    adjoint)
         nbytes = lbm3_workspace_bytes(self.domains, self.options)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self.stream = torch.cuda.current_stream(self.device)
@@ -259,15 +287,48 @@ class Simulation:
     def mass(self) -> np.ndarray:
         return lbm3_mass(self.ctx, self.n)
 
-    def get_state(self):
+    def get_state(self, out=None):
         import torch
-        buf = torch.empty(lbm3_state_bytes(self.ctx), dtype=torch.uint8, device=self.device)
+        n = lbm3_state_bytes(self.ctx)
+        buf = torch.empty(n, dtype=torch.uint8, device=self.device) if out is None else out
+        assert buf.numel() == n and buf.is_contiguous()
         lbm3_get_state(self.ctx, buf.data_ptr())
         return buf
 
     def set_state(self, buf) -> None:
         assert buf.numel() == lbm3_state_bytes(self.ctx) and buf.is_contiguous()
         lbm3_set_state(self.ctx, buf.data_ptr())
+
+    def state_bytes(self) -> int:
+        return lbm3_state_bytes(self.ctx)
+
+    def set_params(self, domain: int, theta_deg, sigma) -> None:
+        lbm3_set_params(self.ctx, domain, theta_deg, sigma)
+
+    def densities(self):
+        """Partial densities of every domain, flat [3][ny][nx] per domain concatenated, zero at
+        solid nodes (the output the adjoint is seeded on)."""
+        import torch
+        parts = []
+        for d, w in enumerate(self.workloads):
+            rho = self.fields(d, velocity=False, force=False)["rho"]
+            fluid = torch.as_tensor(np.asarray(w.solid) == 0, device=self.device)
+            parts.append((rho * fluid).reshape(-1))
+        return torch.cat(parts)
+
+    def adjoint_seed(self, grad_rho, lam) -> None:
+        import torch
+        g = grad_rho.to(device=self.device, dtype=torch.float64).contiguous()
+        assert lam.numel() == self.state_bytes() and lam.is_contiguous()
+        lbm3_adjoint_seed(self.ctx, g.data_ptr(), lam.data_ptr())
+
+    def adjoint_step(self, state, lam_in, lam_out) -> None:
+        n = self.state_bytes()
+        assert state.numel() == n and lam_in.numel() == n and lam_out.numel() == n
+        lbm3_adjoint_step(self.ctx, state.data_ptr(), lam_in.data_ptr(), lam_out.data_ptr())
+
+    def adjoint_grad(self) -> np.ndarray:
+        return lbm3_adjoint_grad(self.ctx, self.n)
 
     def kernel_times(self, nsteps: int):
         return lbm3_kernel_times(self.ctx, nsteps)
