@@ -21,6 +21,33 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per launch of the fused kernel from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB
+# per dispatch), scaled by what the counters read for a 1 GiB device copy in the same process
+# (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0); summaries and commands in profiles/.  Keyed by workload,
+# precision and kernel configuration, valid for the kernel sources with the given digest only.
+KERNEL_SOURCES = ("lbm3_kernels.hip", "lbm3_device.h", "lbm3_internal.h", "lbm3_kernels.h")
+TRAFFIC = {
+    "digest": "5a25da32dbb21d88",
+    ("cylinder_janus", 400, "f32", (0, 16, 16)): (4471.5 * 2.0 + 6969.0) * 1024,
+    ("cylinder_janus_x10", 4000, "f32", (0, 16, 16)): (431797.0 * 2.0 + 698610.1) * 1024,
+}
+
+
+def kernel_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2102_04709_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(w, precision, config):
+    if config is None or kernel_digest() != TRAFFIC["digest"]:
+        return None
+    v = TRAFFIC.get((w.name, w.nx, precision, tuple(config)))
+    return None if v is None else int(v)
+
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
@@ -36,27 +63,87 @@ def timed_run(sim, steps, warmup):
     return time.perf_counter() - t0
 
 
-def roofline(sim, launches=50):
+def roofline(sim, launches=50, traffic=None):
     ms_fill, ms_step = sim.kernel_times(launches)
     nodes = sim.query(1)
     bpl = sim.query(0)
     achieved = bpl * nodes / (ms_step * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": "step_fused", "bytes_per_lup": bpl, "lups_per_launch": int(nodes),
             "ms_per_launch": round(ms_step, 5), "fill_kernel_ms_per_launch": round(ms_fill, 5)}
 
 
-def measure(workloads_, precision, steps, warmup, graph=100, tile=None):
+def measure(workloads_, precision, steps, warmup, graph=100, config=None):
+    """config = (kernel, tile_x, tile_y) as lbm3_autotune returns it; None runs the autotuner."""
     from paper_2102_04709_amd import lbm3
-    sim = lbm3.Simulation(workloads_, precision=precision, graph_block_steps=graph, tile=tile)
-    tile = sim.autotune(3) if tile is None else tile
+    if config is None:
+        sim = lbm3.Simulation(workloads_, precision=precision, graph_block_steps=graph)
+        tile = sim.autotune(3)
+    else:
+        k, tx, ty = config
+        sim = lbm3.Simulation(workloads_, precision=precision, graph_block_steps=graph, kernel=int(k),
+                              tile=(tx, ty) if k == 0 else (0, ty))
+        tile = tuple(config)
     dt = timed_run(sim, steps, warmup)
     nodes = sim.query(1)
+    traffic = traffic_for(workloads_[0], precision, tile) if len(workloads_) == 1 else None
     res = {"mlups": round(nodes * steps / dt / 1e6, 1), "ms_per_step": round(dt / steps * 1e3, 5),
-           "tile": list(tile) if tile else None, "roofline": roofline(sim)}
+           "tile": list(tile) if tile else None, "roofline": roofline(sim, traffic=traffic)}
     sim.close()
     return res, dt
+
+
+def measure_adjoint(w, precision, steps=40, rollout_steps=400, every=100):
+    """Adjoint step throughput (lbm3_adjoint_step over stored forward states, HIP events on the
+    library's stream) and the checkpointed forward + backward rollout of `rollout_steps` steps.
+    Algorithmic bytes per node of one adjoint step: the forward state s_t read, lambda_{t+1}
+    read and lambda_t written, each 9 distributions + 3 densities."""
+    import torch
+    from paper_2102_04709_amd import lbm3, rollout
+    sim = lbm3.Simulation([w], precision=precision, adjoint=True)
+    sim.step(100)
+    nb = sim.state_bytes()
+    states = torch.empty((steps, nb), dtype=torch.uint8, device=sim.device)
+    for t in range(steps):
+        sim.get_state(out=states[t])
+        sim.step(1)
+    gen = torch.Generator(device="cpu").manual_seed(1)
+    g = torch.randn(3 * w.nx * w.ny, generator=gen, dtype=torch.float64).to(sim.device)
+    lam, lam2 = torch.empty(nb, dtype=torch.uint8, device=sim.device), torch.empty(nb, dtype=torch.uint8, device=sim.device)
+    sim.adjoint_seed(g, lam)
+    for t in reversed(range(min(5, steps))):
+        sim.adjoint_step(states[t], lam, lam2)
+        lam, lam2 = lam2, lam
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(sim.stream)
+    for t in reversed(range(steps)):
+        sim.adjoint_step(states[t], lam, lam2)
+        lam, lam2 = lam2, lam
+    ev1.record(sim.stream)
+    ev1.synchronize()
+    ms = ev0.elapsed_time(ev1) / steps
+    nodes = w.nx * w.ny
+    bpl = 3 * (9 * (8 if precision == "f64" else 4) + 3 * (8 if precision == "f64" else 4))
+    achieved = bpl * nodes / (ms * 1e-3) / 1e9
+    res = {"mlups": round(nodes / (ms * 1e-3) / 1e6, 1), "ms_per_step": round(ms, 5),
+           "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                        "kernel": "adjoint step (all kernels of lbm3_adjoint_step)", "bytes_per_lup": bpl,
+                        "lups_per_launch": nodes}}
+    # checkpointed rollout: forward with checkpoints, backward with recompute and adjoint steps
+    s0 = sim.get_state()
+    params = rollout.params_of([w]).requires_grad_(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rho = rollout.rollout(params, sim, rollout_steps, s0, every)
+    (rho * g).sum().backward()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    res["rollout"] = {"steps": rollout_steps, "checkpoint_every": every, "seconds": round(dt, 3),
+                      "mlups_forward_plus_backward": round(nodes * rollout_steps / dt / 1e6, 1)}
+    sim.close()
+    return res
 
 
 def cpu_baseline(w, budget_s=15.0):
@@ -85,8 +172,10 @@ def main():
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--only", default=None,
                     help="run one workload (cylinder_400_f32|f64|f16, cylinder_4000_f32|f64|f16, "
-                         "pillar_sweep_96_f32) and print its measurement")
-    ap.add_argument("--tile", default=None, help="fixed tile 'TX,TY' for --only (skips the autotuner)")
+                         "pillar_sweep_96_f32, adjoint_512_f32|f64) and print its measurement")
+    ap.add_argument("--config", default=None,
+                    help="fixed kernel configuration 'KERNEL,TX,TY' for --only, as the autotuner reports "
+                         "it (0 = tiles TX x TY, 1/2 = strips of 128/256 threads with TY rows)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -108,14 +197,18 @@ def main():
         log("copy calibration: 3 x 1 GiB device-to-device copies")
     if args.only:
         name = args.only
+        if name.startswith("adjoint_512"):
+            r = measure_adjoint(W.inverse_problem(), name.rsplit("_", 1)[1])
+            print(json.dumps({"workload": name, **r}), flush=True)
+            return
         if name.startswith("pillar_sweep"):
             ws, graph = W.pillar_sweep(), 10
         elif name.startswith("cylinder_4000"):
             ws, graph = [W.cylinder_janus_hbm(10)], 10
         else:
             ws, graph = [W.cylinder_janus()], 100
-        tile = tuple(int(v) for v in args.tile.split(",")) if args.tile else None
-        r, _ = measure(ws, name.rsplit("_", 1)[1], args.steps, args.warmup, graph=graph, tile=tile)
+        config = tuple(int(v) for v in args.config.split(",")) if args.config else None
+        r, _ = measure(ws, name.rsplit("_", 1)[1], args.steps, args.warmup, graph=graph, config=config)
         print(json.dumps({"workload": name, **r}), flush=True)
         return
     w = W.cylinder_janus()
@@ -147,6 +240,9 @@ def main():
         r, _ = measure(sweep, "f32", 100, 10, graph=10)
         r["domains"] = len(sweep)
         extra["pillar_sweep_96_f32"] = r
+        for p in ("f32", "f64"):
+            log(f"variant: adjoint step, inverse problem 512x256 {p}")
+            extra[f"adjoint_512_{p}"] = measure_adjoint(W.inverse_problem(), p)
         out["variants"] = extra
         out["roofline_hbm"] = extra["cylinder_4000_f32"]["roofline"]
     if not args.skip_cpu:

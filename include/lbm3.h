@@ -178,15 +178,16 @@ lbm3_status lbm3_adjoint_step(lbm3_ctx *c, const void *dev_state, const void *de
  * (Eq. 15) included.  Synchronises. */
 lbm3_status lbm3_adjoint_grad(lbm3_ctx *c, double *host_grad);
 
-/* Average device time (ms) of one launch of the wetting-fill kernel and of the fused step kernel
- * over nsteps plain steps, from HIP events recorded on the context's stream around each launch.
- * Advances the state by nsteps.  Synchronises. */
+/* Average device time (ms) of one launch of the wetting-fill kernel and of the fused step kernel:
+ * HIP events on the context's stream around nsteps back-to-back fills of the current state and
+ * then nsteps back-to-back fused launches that all compute the same next step into the spare
+ * buffer.  The state does not advance.  Synchronises. */
 lbm3_status lbm3_kernel_times(lbm3_ctx *c, int32_t nsteps, double *ms_fill, double *ms_step);
 
 /* Times the candidate configurations of the fused kernel (tile shapes, strip widths and
  * segment lengths) on the live state and keeps the fastest; returns (kernel, tile_x, tile_y)
- * in choice[3].  Every candidate computes the same result bit for bit; timing them advances
- * the state.  Synchronises. */
+ * in choice[3].  Every candidate computes the same result bit for bit; each candidate's two
+ * warm-up steps advance the state.  Synchronises. */
 lbm3_status lbm3_autotune(lbm3_ctx *c, int32_t steps_per_candidate, int32_t *choice);
 
 /* Information: key 0 = algorithmic bytes per lattice update of the fused kernel (state read

@@ -8,13 +8,13 @@
 // filled C at the solid boundary nodes (Eq. 21-22), stress and pair normals (Eq. 10, 12),
 // interfacial force, post-collision f' and recolouring vectors R (Eq. 1-9, 11, 13-15).
 // Transposes, in reverse order of the forward: streaming (Eq. 16 with every boundary rule, as
-// atomic scatters), the per-node collision + recolouring (Jacobian-transpose products from
-// forward-mode dual numbers run through the same templated code as the forward kernels, one
-// seed per input), the stress divergence, the per-node stress (dual numbers), the colour-gradient
-// stencil, the mass fractions, and the wetting fill (dual numbers over the fill's arithmetic with
-// its discrete choices -- which crossing, which line -- fixed at their forward values).
-// Non-smooth points (the max/min of Eq. 22, clamps, the |G| threshold) take the derivative of the
-// branch the forward took.
+// atomic scatters), the per-node collision + recolouring and the per-position stress (reverse-
+// mode products written out from the forward formulas), the stress divergence, the colour-
+// gradient stencil, the mass fractions, and the wetting fill (its discrete choices -- which
+// crossing, which line -- fixed at their forward values).  Non-smooth points (the max/min of
+// Eq. 22, clamps, the |G| threshold) take the derivative of the branch the forward took: a
+// clamp passes the derivative when its argument lies inside or on the bounds, max/min give it
+// to the first operand on ties.
 #include <hip/hip_runtime.h>
 
 #include "lbm3_adjoint.h"
@@ -23,63 +23,9 @@
 
 namespace lbm3 {
 
-// ---- dual numbers: a value and one directional derivative ------------------------------------
-// The math overloads are hidden friends: found for Dual arguments by argument-dependent lookup
-// only, so plain double/float calls in this namespace still reach the C library functions.
-template <typename T>
-struct Dual {
-  T v, d;
-  __host__ __device__ Dual() : v(0), d(0) {}
-  __host__ __device__ Dual(double x) : v((T)x), d(0) {}
-  __host__ __device__ Dual(T x, T dx, int) : v(x), d(dx) {}
-  friend __device__ Dual operator+(Dual a, Dual b) { return Dual(a.v + b.v, a.d + b.d, 0); }
-  friend __device__ Dual operator-(Dual a, Dual b) { return Dual(a.v - b.v, a.d - b.d, 0); }
-  friend __device__ Dual operator-(Dual a) { return Dual(-a.v, -a.d, 0); }
-  friend __device__ Dual operator*(Dual a, Dual b) { return Dual(a.v * b.v, a.d * b.v + a.v * b.d, 0); }
-  friend __device__ Dual operator/(Dual a, Dual b) {
-    const T r = a.v / b.v;
-    return Dual(r, (a.d - r * b.d) / b.v, 0);
-  }
-  __device__ Dual &operator+=(Dual b) { v += b.v; d += b.d; return *this; }
-  __device__ Dual &operator-=(Dual b) { v -= b.v; d -= b.d; return *this; }
-  friend __device__ bool operator>(Dual a, Dual b) { return a.v > b.v; }
-  friend __device__ bool operator<(Dual a, Dual b) { return a.v < b.v; }
-  friend __device__ bool operator<=(Dual a, Dual b) { return a.v <= b.v; }
-  friend __device__ bool operator>=(Dual a, Dual b) { return a.v >= b.v; }
-  friend __device__ Dual sqrt(Dual a) {
-    const T s = sqrt(a.v);
-    return Dual(s, s > T(0) ? a.d / (T(2) * s) : T(0), 0);
-  }
-  friend __device__ Dual fmin(Dual a, Dual b) { return a.v <= b.v ? a : b; }
-  friend __device__ Dual fmax(Dual a, Dual b) { return a.v >= b.v ? a : b; }
-  friend __device__ Dual fabs(Dual a) { return a.v < T(0) ? -a : a; }
-};
-
-template <>
-__device__ __forceinline__ Dual<float> rcp<Dual<float>>(Dual<float> x) {
-  const float r = __builtin_amdgcn_rcpf(x.v);
-  return Dual<float>(r, -x.d * r * r, 0);
-}
-template <>
-__device__ __forceinline__ Dual<double> rcp<Dual<double>>(Dual<double> x) {
-  const double r = 1.0 / x.v;
-  return Dual<double>(r, -x.d * r * r, 0);
-}
-
-__device__ __forceinline__ void sincos_dual(Dual<double> x, Dual<double> &s, Dual<double> &c) {
-  double sv, cv;
-  sincos(x.v, &sv, &cv);
-  s = Dual<double>(sv, cv * x.d, 0);
-  c = Dual<double>(cv, -sv * x.d, 0);
-}
-
 // Hardware floating-point atomic add (the workspace is ordinary coarse-grained device memory).
 template <typename T>
 __device__ __forceinline__ void aadd(T *p, T v) { unsafeAtomicAdd(p, v); }
-
-// Input number idx of a dual evaluation seeded on input s.
-template <typename T>
-__device__ __forceinline__ Dual<T> seeded(T v, int s, int idx) { return Dual<T>(v, s == idx ? T(1) : T(0), 0); }
 
 // ---- extended grid ---------------------------------------------------------------------------
 __device__ __forceinline__ int64_t aidx(const DomainDev &D, int i, int j) {
@@ -245,32 +191,51 @@ __global__ __launch_bounds__(kThreads) void adj_zero(AdjArgs<S, T> A, int64_t n)
 }
 
 // ---- transposes ----------------------------------------------------------------------------
-// Adjoint of one read in the forward pull of the recoloured populations of direction dir of
-// node q, weighted by coef: the read contributes coef * f'_dir to the destination's total
-// (adjoint lf) and coef * (C_k (f'_dir + w) + w R_k.e_dir) to its partial density k (adjoint
-// mu[k], already permuted for a fluid-exchanging boundary).
+// Zou-He at a boundary node y (Eq. 16 with the Zou-He rule): the unknown totals are affine in
+// the known ones, so the adjoint of a known population d of y gains a term from the adjoints of
+// the unknown populations (and, at the outlet, of the partial densities they carry).
 template <typename T>
-__device__ __forceinline__ void scatter_parts(T *X, int64_t AP, int64_t q, int dir, T coef, const T mu[3], T lf) {
-  const T f = X[(AX_P + dir) * AP + q];
-  const T C0 = X[AX_C * AP + q], C1 = X[(AX_C + 1) * AP + q], C2 = X[(AX_C + 2) * AP + q];
-  const T w = wgt<T>(dir);
-  const int ex = lat_ex(dir), ey = lat_ey(dir);
-  aadd(&X[(AL_P + dir) * AP + q], coef * (lf + mu[0] * C0 + mu[1] * C1 + mu[2] * C2));
-  const T fw = coef * (f + w);
-  aadd(&X[AL_C * AP + q], mu[0] * fw);
-  aadd(&X[(AL_C + 1) * AP + q], mu[1] * fw);
-  aadd(&X[(AL_C + 2) * AP + q], mu[2] * fw);
-  const T a = coef * w * (mu[0] - mu[2]), b = coef * w * (mu[1] - mu[2]);
-  if (ex) {
-    aadd(&X[(AL_P + 9) * AP + q], a * T(ex));
-    aadd(&X[(AL_P + 11) * AP + q], b * T(ex));
+__device__ __forceinline__ T zh_add(const DomainDev &D, bool inlet, int d, const T *Lf, const T *Lr, int64_t yli,
+                                    const T Cy[3]) {
+  const int64_t P = D.plane;
+  if (inlet) {
+    const T u = (T)D.u_in;
+    const T ir = T(1) / (T(1) - u);
+    const T l1 = Lf[1 * P + yli] + Lr[2 * P + yli];  // the inflow is fluid 3
+    const T l5 = Lf[5 * P + yli] + Lr[2 * P + yli];
+    const T l8 = Lf[8 * P + yli] + Lr[2 * P + yli];
+    const T lw = (T(2.0 / 3.0) * l1 + (l5 + l8) / T(6)) * u;
+    // d rho_w / d ft_d: ft0, ft2, ft4 once, ft3, ft6, ft7 twice
+    T add = lw * ir * (d == 3 || d == 6 || d == 7 ? T(2) : (d == 0 || d == 2 || d == 4 ? T(1) : T(0)));
+    if (d == 3) add += l1;
+    if (d == 7) add += l5;
+    if (d == 6) add += l8;
+    if (d == 2) add += T(0.5) * (l8 - l5);
+    if (d == 4) add += T(0.5) * (l5 - l8);
+    return add;
   }
-  if (ey) {
-    aadd(&X[(AL_P + 10) * AP + q], a * T(ey));
-    aadd(&X[(AL_P + 12) * AP + q], b * T(ey));
-  }
+  const T mc = Lr[yli] * Cy[0] + Lr[P + yli] * Cy[1] + Lr[2 * P + yli] * Cy[2];
+  const T l3 = Lf[3 * P + yli] + mc, l6 = Lf[6 * P + yli] + mc, l7 = Lf[7 * P + yli] + mc;
+  const T lw = -(T(2.0 / 3.0) * l3 + (l7 + l6) / T(6));
+  // d (rho_out u_x) / d ft_d: ft0, ft2, ft4 once, ft1, ft5, ft8 twice
+  T add = lw * (d == 1 || d == 5 || d == 8 ? T(2) : (d == 0 || d == 2 || d == 4 ? T(1) : T(0)));
+  if (d == 1) add += l3;
+  if (d == 5) add += l7;
+  if (d == 8) add += l6;
+  if (d == 2) add += T(0.5) * (l7 - l6);
+  if (d == 4) add += T(0.5) * (l6 - l7);
+  return add;
 }
 
+// Adjoint of streaming in gather form: each fluid node x collects the adjoints of its own
+// post-collision data f'_d(x) and R(x) (and of its C through the recoloured parts) from every
+// read of them in the forward pull:
+//   - the node y = x + e_d pulls f'_d(x) (populations crossing the fluid-exchanging boundary
+//     swap the adjoints of fluids 1 and 3; a Zou-He node adds the unknowns' dependence);
+//   - the same y, when its link opposite to d is cut with q < 1/2 and x + 2 e_d is solid, reads
+//     f'_d(x) again with weight 1 - 2q (interpolated bounce-back);
+//   - x itself, for each of its own solid links (halfway or interpolated bounce-back).
+// No atomics: every adjoint of x's data is written by x's thread.
 template <typename S, typename T>
 __global__ __launch_bounds__(kThreads) void adj_stream(AdjArgs<S, T> A, int64_t tplane) {
   const WorkItem wk = A.work[blockIdx.x];
@@ -278,103 +243,259 @@ __global__ __launch_bounds__(kThreads) void adj_stream(AdjArgs<S, T> A, int64_t 
   int i, j;
   if (!tile_node(wk, i, j) || !fluid_node(A.flags, D, i, j)) return;
   const int64_t AP = A.aplane;
+  const int64_t P = D.plane;
   const int64_t li = plane_index(i, j, D.pitch);
   const int64_t q = aidx(D, i, j);
-  T lf[9], mu[3];
+  const T *Lf = A.lin + 9 * D.base;
+  const T *Lr = A.lin + 9 * tplane + 3 * D.base;
+  const bool zh = D.bcx == BCX_ZOUHE;
+  const T C[3] = {A.X[AX_C * AP + q], A.X[(AX_C + 1) * AP + q], A.X[(AX_C + 2) * AP + q]};
+  T fp[9];
 #pragma unroll
-  for (int a = 0; a < 9; ++a) lf[a] = A.lin[9 * D.base + a * D.plane + li];
+  for (int a = 0; a < 9; ++a) fp[a] = A.X[(AX_P + a) * AP + q];
+  T lP[13], lC[3] = {T(0), T(0), T(0)};
 #pragma unroll
-  for (int k = 0; k < 3; ++k) mu[k] = A.lin[9 * tplane + 3 * D.base + k * D.plane + li];
-  if (D.bcx == BCX_ZOUHE && (i == 0 || i == D.nx - 1)) {
-    // Zou-He: the unknown totals are affine in the known ones, which the columns next to the
-    // boundary supply (no solid node lies within three columns of it and y is periodic).
+  for (int c = 0; c < 13; ++c) lP[c] = T(0);
+  // a read of f'_dir(x) with weight coef into a node whose total has adjoint lfv and whose
+  // partial densities have adjoints m[3] (the recoloured part k is C_k (f' + w) + w R_k.e)
+  auto take = [&](int dir, T coef, T lfv, T m0, T m1, T m2) {
+    const T w = wgt<T>(dir);
+    const int ex = lat_ex(dir), ey = lat_ey(dir);
+    lP[dir] += coef * (lfv + m0 * C[0] + m1 * C[1] + m2 * C[2]);
+    const T fw = coef * (fp[dir] + w);
+    lC[0] += m0 * fw;
+    lC[1] += m1 * fw;
+    lC[2] += m2 * fw;
+    const T a = coef * w * (m0 - m2), b = coef * w * (m1 - m2);
+    if (ex) {
+      lP[9] += a * T(ex);
+      lP[11] += b * T(ex);
+    }
+    if (ey) {
+      lP[10] += a * T(ey);
+      lP[12] += b * T(ey);
+    }
+  };
+#pragma unroll
+  for (int d = 0; d < 9; ++d) {
+    const int ex = lat_ex(d), ey = lat_ey(d);
+    const int yx = i + ex;
+    if (zh && (yx < 0 || yx >= D.nx)) continue;  // nothing is pulled out through a Zou-He boundary
+    int yi = yx, yj = j + ey;
+    cmap(D, yi, yj);
+    if (solid_at(A.flags, D, yi, yj)) continue;
+    const int64_t yli = plane_index(yi, yj, D.pitch);
+    T lfv = Lf[d * P + yli];
+    const T m0 = Lr[yli], m1 = Lr[P + yli], m2 = Lr[2 * P + yli];
+    if (zh && (yi == 0 || yi == D.nx - 1)) {
+      const int64_t yq = aidx(D, yi, yj);
+      const T Cy[3] = {A.X[AX_C * AP + yq], A.X[(AX_C + 1) * AP + yq], A.X[(AX_C + 2) * AP + yq]};
+      lfv += zh_add(D, yi == 0, d, Lf, Lr, yli, Cy);
+    }
+    const bool crossed = D.bcx == BCX_SWAP13 && (yx < 0 || yx >= D.nx);
+    if (crossed) take(d, T(1), lfv, m2, m1, m0);
+    else take(d, T(1), lfv, m0, m1, m2);
+    if (d != 0 && (A.flags[D.base + yli] & FL_CURVED) && D.n_ibb > 0) {
+      int zi = yx + ex, zj = j + 2 * ey;
+      cmap(D, zi, zj);
+      if (solid_at(A.flags, D, zi, zj)) {
+        const int a = lat_opp(d);
+        const T qa = (T)find_ibb(A.ibb, D, yli)->q[a - 1];
+        if (qa < T(0.5)) take(d, T(1) - T(2) * qa, Lf[a * P + yli], m0, m1, m2);
+      }
+    }
+  }
+  // own solid links
+  const uint8_t fl = A.flags[D.base + li];
+  const IbbNode *ib = ((fl & FL_CURVED) && D.n_ibb > 0) ? find_ibb(A.ibb, D, li) : nullptr;
+  const T mu0 = Lr[li], mu1 = Lr[P + li], mu2 = Lr[2 * P + li];
+#pragma unroll
+  for (int a = 1; a < 9; ++a) {
+    const int ex = lat_ex(a), ey = lat_ey(a);
+    const int sx = i - ex;
+    if (zh && (sx < 0 || sx >= D.nx)) continue;
+    int si = sx, sj = j - ey;
+    cmap(D, si, sj);
+    if (!solid_at(A.flags, D, si, sj)) continue;
+    const int ab = lat_opp(a);
+    const T qd = ib ? (T)ib->q[a - 1] : T(0.5);
+    const T lfa = Lf[a * P + li];
+    int ni = i + ex, nj = j + ey;
+    cmap(D, ni, nj);
+    if (qd < T(0.5) && !solid_at(A.flags, D, ni, nj)) {
+      take(ab, T(2) * qd, lfa, mu0, mu1, mu2);  // the neighbour's share is gathered there
+    } else if (qd < T(0.5)) {
+      take(ab, T(1), lfa, mu0, mu1, mu2);
+    } else {
+      const T c1 = rcp(T(2) * qd), c2 = T(1) - c1;
+      take(ab, c1, lfa, mu0, mu1, mu2);
+      if (c2 != T(0)) take(a, c2, lfa, mu0, mu1, mu2);
+    }
+  }
+  if (zh && i == D.nx - 1) {
+    // the outflowing unknowns carry the node's own composition: d ra_k / d C_k = f3 + f6 + f7
     T ft[9];
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
-      const int si = i - lat_ex(a);
-      int ii = si, jj = j - lat_ey(a);
+      const int sx = i - lat_ex(a);
+      int ii = sx, jj = j - lat_ey(a);
       cmap(D, ii, jj);
-      ft[a] = (si < 0 || si >= D.nx) ? T(0) : A.X[(AX_P + a) * AP + aidx(D, ii, jj)] + wgt<T>(a);
+      ft[a] = sx >= D.nx ? T(0) : A.X[(AX_P + a) * AP + aidx(D, ii, jj)] + wgt<T>(a);
     }
-    if (i == 0) {
-      const T u = (T)D.u_in;
-      const T ir = T(1) / (T(1) - u);
-      const T r[9] = {ir, 0, ir, 2 * ir, ir, 0, 2 * ir, 2 * ir, 0};  // d rho_w / d ft_k
-      const T l1 = lf[1] + mu[2], l5 = lf[5] + mu[2], l8 = lf[8] + mu[2];  // inflow is fluid 3
-      const T lw = (T(2.0 / 3.0) * l1 + (l5 + l8) / T(6)) * u;
-#pragma unroll
-      for (int k = 0; k < 9; ++k) {
-        if (k == 1 || k == 5 || k == 8) continue;
-        T add = lw * r[k];
-        if (k == 3) add += l1;
-        if (k == 7) add += l5;
-        if (k == 6) add += l8;
-        if (k == 2) add += T(0.5) * (l8 - l5);
-        if (k == 4) add += T(0.5) * (l5 - l8);
-        lf[k] += add;
-      }
-    } else {
-      const T ro = (T)D.rho_out;
-      const T s[9] = {1, 2, 1, 0, 1, 2, 0, 0, 2};  // d (rho_out u_x) / d ft_k
-      const T C0 = A.X[AX_C * AP + q], C1 = A.X[(AX_C + 1) * AP + q], C2 = A.X[(AX_C + 2) * AP + q];
-      const T ux = -T(1) + (ft[0] + ft[2] + ft[4] + T(2) * (ft[1] + ft[5] + ft[8])) / ro;
-      const T f3 = ft[1] - T(2.0 / 3.0) * ro * ux;
-      const T f7 = ft[5] + T(0.5) * (ft[2] - ft[4]) - ro * ux / T(6);
-      const T f6 = ft[8] - T(0.5) * (ft[2] - ft[4]) - ro * ux / T(6);
-      const T su = f3 + f6 + f7;  // outflow carries the node's own composition
-      aadd(&A.X[AL_C * AP + q], mu[0] * su);
-      aadd(&A.X[(AL_C + 1) * AP + q], mu[1] * su);
-      aadd(&A.X[(AL_C + 2) * AP + q], mu[2] * su);
-      const T mc = mu[0] * C0 + mu[1] * C1 + mu[2] * C2;
-      const T l3 = lf[3] + mc, l6 = lf[6] + mc, l7 = lf[7] + mc;
-      const T lw = -(T(2.0 / 3.0) * l3 + (l7 + l6) / T(6));
-#pragma unroll
-      for (int k = 0; k < 9; ++k) {
-        if (k == 3 || k == 6 || k == 7) continue;
-        T add = lw * s[k];
-        if (k == 1) add += l3;
-        if (k == 5) add += l7;
-        if (k == 8) add += l6;
-        if (k == 2) add += T(0.5) * (l7 - l6);
-        if (k == 4) add += T(0.5) * (l6 - l7);
-        lf[k] += add;
-      }
-    }
+    const T ro = (T)D.rho_out;
+    const T ux = -T(1) + (ft[0] + ft[2] + ft[4] + T(2) * (ft[1] + ft[5] + ft[8])) / ro;
+    const T f3 = ft[1] - T(2.0 / 3.0) * ro * ux;
+    const T f7 = ft[5] + T(0.5) * (ft[2] - ft[4]) - ro * ux / T(6);
+    const T f6 = ft[8] - T(0.5) * (ft[2] - ft[4]) - ro * ux / T(6);
+    const T su = f3 + f6 + f7;
+    lC[0] += mu0 * su;
+    lC[1] += mu1 * su;
+    lC[2] += mu2 * su;
   }
-  const uint8_t fl = A.flags[D.base + li];
-  const IbbNode *ib = ((fl & FL_CURVED) && D.n_ibb > 0) ? find_ibb(A.ibb, D, li) : nullptr;
 #pragma unroll
-  for (int a = 0; a < 9; ++a) {
-    const int ex = lat_ex(a), ey = lat_ey(a);
-    const int sx = i - ex;
-    if (D.bcx == BCX_ZOUHE && (sx < 0 || sx >= D.nx)) continue;  // unknown: handled above
-    int si = sx, sj = j - ey;
-    cmap(D, si, sj);
-    if (!solid_at(A.flags, D, si, sj)) {
-      const bool crossed = D.bcx == BCX_SWAP13 && (sx < 0 || sx >= D.nx);
-      const T m[3] = {crossed ? mu[2] : mu[0], mu[1], crossed ? mu[0] : mu[2]};
-      scatter_parts(A.X, AP, aidx(D, si, sj), a, T(1), m, lf[a]);
-    } else {
-      const int ab = lat_opp(a);
-      const T qd = ib ? (T)ib->q[a - 1] : T(0.5);
-      int ni = i + ex, nj = j + ey;
-      cmap(D, ni, nj);
-      if (qd < T(0.5) && !solid_at(A.flags, D, ni, nj)) {
-        scatter_parts(A.X, AP, q, ab, T(2) * qd, mu, lf[a]);
-        scatter_parts(A.X, AP, aidx(D, ni, nj), ab, T(1) - T(2) * qd, mu, lf[a]);
-      } else if (qd < T(0.5)) {
-        scatter_parts(A.X, AP, q, ab, T(1), mu, lf[a]);
-      } else {
-        const T c1 = rcp(T(2) * qd), c2 = T(1) - c1;
-        scatter_parts(A.X, AP, q, ab, c1, mu, lf[a]);
-        if (c2 != T(0)) scatter_parts(A.X, AP, q, a, c2, mu, lf[a]);
-      }
-    }
-  }
+  for (int c = 0; c < 13; ++c) A.X[(AL_P + c) * AP + q] = lP[c];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) A.X[(AL_C + c) * AP + q] = lC[c];
 }
 
-// Adjoint of the per-node collision and recolouring: inputs f (9), F_s (2), C (3), rho (1),
-// n (6) and g(X) of the three pairs (3); outputs f' (9) and R (4).
+// Reverse-mode product of collide_shifted (Eq. 1-9, 11) followed by recolour_R (Eq. 13-15):
+// given the adjoints lfd[9] of the post-collision shifted populations and lR[4] of the
+// recolouring vectors, returns the adjoints of the inputs f[9], the interfacial force (lFx, lFy),
+// the mass fractions C[3] and total density rt (r_k = C_k rt), the pair normals n[6] and the
+// factors g(X_kl)[3].  The forward intermediates are recomputed in the same order.
+template <typename T>
+__device__ __forceinline__ void collide_recolour_vjp(const T f[9], T Fxi, T Fyi, const T C[3], T rt, const T nrm[6],
+                                                     const KT<T> &K, const T lfd[9], const T lR[4], T lf[9],
+                                                     T &lFx, T &lFy, T lC[3], T &lrt, T ln[6], T lgX[3]) {
+  const T r0 = C[0] * rt, r1 = C[1] * rt, r2 = C[2] * rt;
+  // ---- forward of the collision
+  const T s14 = f[1] + f[2] + f[3] + f[4], s58 = f[5] + f[6] + f[7] + f[8];
+  const T drho = f[0] + s14 + s58;
+  const T m1 = -T(4) * f[0] - s14 + T(2) * s58;
+  const T m2 = T(4) * f[0] - T(2) * s14 + s58;
+  const T jx = f[1] - f[3] + f[5] - f[6] - f[7] + f[8];
+  const T m4 = -T(2) * f[1] + T(2) * f[3] + f[5] - f[6] - f[7] + f[8];
+  const T jy = f[2] - f[4] + f[5] + f[6] - f[7] - f[8];
+  const T m6 = -T(2) * f[2] + T(2) * f[4] + f[5] + f[6] - f[7] - f[8];
+  const T m7 = f[1] - f[2] + f[3] - f[4];
+  const T m8 = f[5] - f[6] + f[7] - f[8];
+  const T rho = T(1) + drho;
+  const T Fx = Fxi + rho * K.g0, Fy = Fyi + rho * K.g1;
+  const T irho = rcp(rho);
+  const T ux = (jx + T(0.5) * Fx) * irho, uy = (jy + T(0.5) * Fy) * irho;
+  const T sum = r0 * K.inu[0] + r1 * K.inu[1] + r2 * K.inu[2];
+  const T den1 = T(0.5) * sum + T(3);
+  const T s1 = sum * rcp(den1);
+  const T s4 = T(8) * (T(2) - s1) * rcp(T(8) - s1);
+  const T ruu = rho * (ux * ux + uy * uy);
+  const T uF = ux * Fx + uy * Fy;
+  const T h1 = T(1) - T(0.5) * s1, h4 = T(1) - T(0.5) * s4;
+  const T A1 = m1 + T(2) * drho - T(3) * ruu, A2 = m2 - drho + T(3) * ruu;
+  const T A4 = m4 + rho * ux, A6 = m6 + rho * uy;
+  const T Pxy = ux * ux - uy * uy, A7 = m7 - rho * Pxy;
+  const T A8 = m8 - rho * ux * uy;
+  const T Q7 = ux * Fx - uy * Fy, Q8 = ux * Fy + uy * Fx;
+  // ---- adjoint: fd = f - M^T d, so ld_i = -(M lfd)_i
+  const T L0 = lfd[0], L1 = lfd[1], L2 = lfd[2], L3 = lfd[3], L4 = lfd[4];
+  const T L5 = lfd[5], L6 = lfd[6], L7 = lfd[7], L8 = lfd[8];
+  const T q14 = L1 + L2 + L3 + L4, q58 = L5 + L6 + L7 + L8;
+  const T ld1 = -(-T(4) * L0 - q14 + T(2) * q58);
+  const T ld2 = -(T(4) * L0 - T(2) * q14 + q58);
+  const T ld3 = -(L1 - L3 + L5 - L6 - L7 + L8);
+  const T ld4 = -(-T(2) * L1 + T(2) * L3 + L5 - L6 - L7 + L8);
+  const T ld5 = -(L2 - L4 + L5 + L6 - L7 - L8);
+  const T ld6 = -(-T(2) * L2 + T(2) * L4 + L5 + L6 - L7 - L8);
+  const T ld7 = -(L1 - L2 + L3 - L4);
+  const T ld8 = -(L5 - L6 + L7 - L8);
+  // d1 = (s1 A1 - 6 h1 uF)/36, d2 = (s1 A2 + 6 h1 uF)/36, d3 = -Fx/6, d4 = (s4 A4 + h4 Fx)/12,
+  // d5 = -Fy/6, d6 = (s4 A6 + h4 Fy)/12, d7 = (s1 A7 - 2 h1 Q7)/4, d8 = (s1 A8 - h1 Q8)/4
+  const T e1 = ld1 * T(1.0 / 36.0), e2 = ld2 * T(1.0 / 36.0), e4 = ld4 * T(1.0 / 12.0);
+  const T e6 = ld6 * T(1.0 / 12.0), e7 = ld7 * T(0.25), e8 = ld8 * T(0.25);
+  T ls1 = e1 * A1 + e2 * A2 + e7 * A7 + e8 * A8;
+  T ls4 = e4 * A4 + e6 * A6;
+  const T lh1 = T(6) * uF * (e2 - e1) - T(2) * Q7 * e7 - Q8 * e8;
+  const T lh4 = Fx * e4 + Fy * e6;
+  const T luF = T(6) * h1 * (e2 - e1);
+  const T lA1 = s1 * e1, lA2 = s1 * e2, lA4 = s4 * e4, lA6 = s4 * e6, lA7 = s1 * e7, lA8 = s1 * e8;
+  const T lQ7 = -T(2) * h1 * e7, lQ8 = -h1 * e8;
+  T lFxt = -ld3 * T(1.0 / 6.0) + h4 * e4;
+  T lFyt = -ld5 * T(1.0 / 6.0) + h4 * e6;
+  const T lruu = T(3) * (lA2 - lA1);
+  T ldrho = T(2) * lA1 - lA2;
+  T lrho = ux * lA4 + uy * lA6 - Pxy * lA7 - ux * uy * lA8 + (ux * ux + uy * uy) * lruu;
+  const T lPxy = -rho * lA7;
+  T lux = rho * lA4 - rho * uy * lA8 + Fx * lQ7 + Fy * lQ8 + T(2) * ux * lPxy + Fx * luF + T(2) * rho * ux * lruu;
+  T luy = rho * lA6 - rho * ux * lA8 - Fy * lQ7 + Fx * lQ8 - T(2) * uy * lPxy + Fy * luF + T(2) * rho * uy * lruu;
+  lFxt += ux * lQ7 + uy * lQ8 + ux * luF;
+  lFyt += -uy * lQ7 + ux * lQ8 + uy * luF;
+  // h = 1 - s/2; s4 = 8 (2 - s1) / (8 - s1); s1 = sum / (sum/2 + 3)
+  ls1 += -T(0.5) * lh1;
+  ls4 += -T(0.5) * lh4;
+  const T i8 = rcp(T(8) - s1);
+  ls1 += ls4 * (-T(48) * i8 * i8);
+  const T id1 = rcp(den1);
+  const T lsum = ls1 * T(3) * id1 * id1;
+  // u = (j + F/2) / rho
+  const T ljx = lux * irho, ljy = luy * irho;
+  lFxt += T(0.5) * lux * irho;
+  lFyt += T(0.5) * luy * irho;
+  const T lirho = lux * (jx + T(0.5) * Fx) + luy * (jy + T(0.5) * Fy);
+  lrho += -lirho * irho * irho;
+  // F = F_s + rho g
+  lFx = lFxt;
+  lFy = lFyt;
+  lrho += K.g0 * lFxt + K.g1 * lFyt;
+  ldrho += lrho;
+  // moments back to the populations: lf = lfd + M^T (ldrho, lm1, lm2, ljx, lm4, ljy, lm6, lm7, lm8)
+  const T lm1 = lA1, lm2 = lA2, lm4 = lA4, lm6 = lA6, lm7 = lA7, lm8 = lA8;
+  lf[0] = L0 + ldrho - T(4) * lm1 + T(4) * lm2;
+  lf[1] = L1 + ldrho - lm1 - T(2) * lm2 + ljx - T(2) * lm4 + lm7;
+  lf[2] = L2 + ldrho - lm1 - T(2) * lm2 + ljy - T(2) * lm6 - lm7;
+  lf[3] = L3 + ldrho - lm1 - T(2) * lm2 - ljx + T(2) * lm4 + lm7;
+  lf[4] = L4 + ldrho - lm1 - T(2) * lm2 - ljy + T(2) * lm6 - lm7;
+  lf[5] = L5 + ldrho + T(2) * lm1 + lm2 + ljx + lm4 + ljy + lm6 + lm8;
+  lf[6] = L6 + ldrho + T(2) * lm1 + lm2 - ljx - lm4 + ljy + lm6 - lm8;
+  lf[7] = L7 + ldrho + T(2) * lm1 + lm2 - ljx - lm4 - ljy - lm6 + lm8;
+  lf[8] = L8 + ldrho + T(2) * lm1 + lm2 + ljx + lm4 - ljy - lm6 - lm8;
+  // ---- recolouring vectors
+  const T irt = rcp(rt);
+  const T P = T(35) * r0 * r1 * r2 * irt * irt * irt;
+  const T r3 = fmin(fmax(P, T(0)), T(1));
+  const T b0 = K.b0;
+  const T b12 = b0 + b0 * r3 * K.gX[0], b13 = b0 + b0 * r3 * K.gX[1], b23 = b0 + b0 * r3 * K.gX[2];
+  const T a12 = b12 * r0 * r1 * irt, a13 = b13 * r0 * r2 * irt, a23 = b23 * r1 * r2 * irt;
+  const T la12 = (lR[0] - lR[2]) * nrm[0] + (lR[1] - lR[3]) * nrm[1];
+  const T la13 = lR[0] * nrm[2] + lR[1] * nrm[3];
+  const T la23 = lR[2] * nrm[4] + lR[3] * nrm[5];
+  ln[0] = (lR[0] - lR[2]) * a12;
+  ln[1] = (lR[1] - lR[3]) * a12;
+  ln[2] = lR[0] * a13;
+  ln[3] = lR[1] * a13;
+  ln[4] = lR[2] * a23;
+  ln[5] = lR[3] * a23;
+  const T lb12 = la12 * r0 * r1 * irt, lb13 = la13 * r0 * r2 * irt, lb23 = la23 * r1 * r2 * irt;
+  T lr0 = lsum * K.inu[0] + (la12 * b12 * r1 + la13 * b13 * r2) * irt;
+  T lr1 = lsum * K.inu[1] + (la12 * b12 * r0 + la23 * b23 * r2) * irt;
+  T lr2 = lsum * K.inu[2] + (la13 * b13 * r0 + la23 * b23 * r1) * irt;
+  T lirt = la12 * b12 * r0 * r1 + la13 * b13 * r0 * r2 + la23 * b23 * r1 * r2;
+  lgX[0] = b0 * r3 * lb12;
+  lgX[1] = b0 * r3 * lb13;
+  lgX[2] = b0 * r3 * lb23;
+  const T lr3 = b0 * (lb12 * K.gX[0] + lb13 * K.gX[1] + lb23 * K.gX[2]);
+  const T lP = (P >= T(0) && P <= T(1)) ? lr3 : T(0);
+  const T i3 = irt * irt * irt;
+  lr0 += lP * T(35) * r1 * r2 * i3;
+  lr1 += lP * T(35) * r0 * r2 * i3;
+  lr2 += lP * T(35) * r0 * r1 * i3;
+  lirt += lP * T(105) * r0 * r1 * r2 * irt * irt;
+  // r_k = C_k rt
+  lC[0] = lr0 * rt;
+  lC[1] = lr1 * rt;
+  lC[2] = lr2 * rt;
+  lrt = lr0 * C[0] + lr1 * C[1] + lr2 * C[2] - lirt * irt * irt;
+}
+
+// Adjoint of the per-node collision and recolouring.
 template <typename S, typename T>
 __global__ __launch_bounds__(kThreads) void adj_collide(AdjArgs<S, T> A) {
   const WorkItem wk = A.work[blockIdx.x];
@@ -385,55 +506,33 @@ __global__ __launch_bounds__(kThreads) void adj_collide(AdjArgs<S, T> A) {
     const int64_t AP = A.aplane;
     const int64_t li = plane_index(i, j, D.pitch);
     const int64_t q = aidx(D, i, j);
-    T in[24];
+    const KT<T> K = make_kt<T>(D);
+    T f[9], C[3], nrm[6], lfd[9], lR[4];
 #pragma unroll
-    for (int a = 0; a < 9; ++a) in[a] = load_s<S, T>(A.fin + 9 * D.base + a * D.plane + li);
-    in[9] = A.X[AX_F * AP + q];
-    in[10] = A.X[(AX_F + 1) * AP + q];
+    for (int a = 0; a < 9; ++a) f[a] = load_s<S, T>(A.fin + 9 * D.base + a * D.plane + li);
 #pragma unroll
-    for (int c = 0; c < 4; ++c) in[11 + c] = A.X[(AX_C + c) * AP + q];
+    for (int c = 0; c < 3; ++c) C[c] = A.X[(AX_C + c) * AP + q];
+    const T rt = A.X[(AX_C + 3) * AP + q];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) in[15 + c] = A.X[(AX_N + c) * AP + q];
+    for (int c = 0; c < 6; ++c) nrm[c] = A.X[(AX_N + c) * AP + q];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) in[21 + c] = (T)D.gX[c];
-    T lo[13];
+    for (int a = 0; a < 9; ++a) lfd[a] = A.X[(AL_P + a) * AP + q];
 #pragma unroll
-    for (int c = 0; c < 13; ++c) lo[c] = A.X[(AL_P + c) * AP + q];
-    T lc[4];
+    for (int c = 0; c < 4; ++c) lR[c] = A.X[(AL_P + 9 + c) * AP + q];
+    T lf[9], lFx, lFy, lC[3], lrt, ln[6], lgX[3];
+    collide_recolour_vjp(f, A.X[AX_F * AP + q], A.X[(AX_F + 1) * AP + q], C, rt, nrm, K, lfd, lR, lf, lFx, lFy,
+                         lC, lrt, ln, lgX);
 #pragma unroll
-    for (int c = 0; c < 4; ++c) lc[c] = A.X[(AL_C + c) * AP + q];
-#pragma unroll 1
-    for (int s = 0; s < 24; ++s) {
-      using DT = Dual<T>;
-      DT f[9];
+    for (int a = 0; a < 9; ++a) A.lout[9 * D.base + a * D.plane + li] = lf[a];
+    A.X[AL_F * AP + q] = lFx;
+    A.X[(AL_F + 1) * AP + q] = lFy;
 #pragma unroll
-      for (int a = 0; a < 9; ++a) f[a] = seeded(in[a], s, a);
-      DT Fx = seeded(in[9], s, 9), Fy = seeded(in[10], s, 10);
-      const DT C0 = seeded(in[11], s, 11), C1 = seeded(in[12], s, 12), C2 = seeded(in[13], s, 13);
-      const DT rt = seeded(in[14], s, 14);
-      DT nrm[6];
+    for (int c = 0; c < 3; ++c) A.X[(AL_C + c) * AP + q] += lC[c];
+    A.X[(AL_C + 3) * AP + q] += lrt;
 #pragma unroll
-      for (int c = 0; c < 6; ++c) nrm[c] = seeded(in[15 + c], s, 15 + c);
-      KT<DT> K = make_kt<DT>(D);
+    for (int c = 0; c < 6; ++c) A.X[(AL_N + c) * AP + q] = ln[c];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) K.gX[c] = seeded(in[21 + c], s, 21 + c);
-      const DT r0 = C0 * rt, r1 = C1 * rt, r2 = C2 * rt;
-      DT fd[9], ux, uy, Rv[4];
-      collide_shifted(f, Fx, Fy, r0, r1, r2, K, fd, ux, uy);
-      recolour_R(r0, r1, r2, rt, nrm, K, Rv);
-      T g = T(0);
-#pragma unroll
-      for (int a = 0; a < 9; ++a) g += lo[a] * fd[a].d;
-#pragma unroll
-      for (int c = 0; c < 4; ++c) g += lo[9 + c] * Rv[c].d;
-      if (s < 9) A.lout[9 * D.base + s * D.plane + li] = g;
-      else if (s < 11) A.X[(AL_F + s - 9) * AP + q] = g;
-      else if (s < 15) lc[s - 11] += g;
-      else if (s < 21) A.X[(AL_N + s - 15) * AP + q] = g;
-      else graw[s - 21] = (double)g;
-    }
-#pragma unroll
-    for (int c = 0; c < 4; ++c) A.X[(AL_C + c) * AP + q] = lc[c];
+    for (int c = 0; c < 3; ++c) graw[c] = (double)lgX[c];
   }
   block_add(graw, A.raw + 9 * wk.dom + 3);
 }
@@ -461,8 +560,58 @@ __global__ __launch_bounds__(kThreads) void adj_div(AdjArgs<S, T> A) {
   }
 }
 
-// Adjoint of the per-position stress and normals: inputs C (3), gradients (6), rho (1) and
-// sigma (3).
+// Reverse-mode product of pair_stress (Eq. 10 with the normals of Eq. 13): given the adjoints of
+// the stress (lt[3]) and of the pair normals (ln[6]), accumulates the adjoints of C[3], of the
+// colour gradients g[3][2], of rho and of the tensions sigma[3].
+template <typename T>
+__device__ __forceinline__ void pair_stress_vjp(const T cc[3], const T g[3][2], T rho, const T sig[3], T eps,
+                                                const T lt[3], const T ln[6], T lc[3], T lg[3][2], T &lrho,
+                                                T lsig[3]) {
+  const int pk[3] = {0, 0, 1}, pl[3] = {1, 2, 2};
+#pragma unroll
+  for (int pr = 0; pr < 3; ++pr) {
+    const int k = pk[pr], l = pl[pr];
+    lsig[pr] = T(0);
+    const T Gx = cc[l] * g[k][0] - cc[k] * g[l][0];
+    const T Gy = cc[l] * g[k][1] - cc[k] * g[l][1];
+    const T mag = sqrt(Gx * Gx + Gy * Gy);
+    if (!(mag > eps)) continue;  // stress and normal are the constant zero there
+    const T rk = cc[k] * rho, rl = cc[l] * rho;
+    const T Q = T(1e6) * rk * rl;
+    const T Akl = fmin(fmax(Q, T(0)), T(1));
+    const T im = rcp(mag);
+    const T nx = Gx * im, ny = Gy * im;
+    const T S = sig[pr] * Akl;
+    // T_pair = S (Gy^2, -Gx Gy, Gx^2) / |G|
+    const T X = lt[0] * Gy * Gy - lt[1] * Gx * Gy + lt[2] * Gx * Gx;
+    const T lS = X * im;
+    T lGx = S * (T(2) * lt[2] * Gx - lt[1] * Gy) * im;
+    T lGy = S * (T(2) * lt[0] * Gy - lt[1] * Gx) * im;
+    const T lmag = -S * lS * im;
+    lGx += lmag * nx;
+    lGy += lmag * ny;
+    // n = G / |G|: lG += (ln - n (n . ln)) / |G|
+    const T lnx = ln[2 * pr], lny = ln[2 * pr + 1];
+    const T nl = nx * lnx + ny * lny;
+    lGx += (lnx - nx * nl) * im;
+    lGy += (lny - ny * nl) * im;
+    lsig[pr] = lS * Akl;
+    const T lQ = (Q >= T(0) && Q <= T(1)) ? lS * sig[pr] : T(0);
+    const T lrk = T(1e6) * rl * lQ, lrl = T(1e6) * rk * lQ;
+    lc[k] += lrk * rho;
+    lc[l] += lrl * rho;
+    lrho += lrk * cc[k] + lrl * cc[l];
+    // G = C_l g_k - C_k g_l
+    lc[l] += lGx * g[k][0] + lGy * g[k][1];
+    lc[k] -= lGx * g[l][0] + lGy * g[l][1];
+    lg[k][0] += lGx * cc[l];
+    lg[k][1] += lGy * cc[l];
+    lg[l][0] -= lGx * cc[k];
+    lg[l][1] -= lGy * cc[k];
+  }
+}
+
+// Adjoint of the per-position stress and normals.
 template <typename S, typename T>
 __global__ __launch_bounds__(kThreads) void adj_stress(AdjArgs<S, T> A) {
   const WorkItem wk = A.work[blockIdx.x];
@@ -472,58 +621,45 @@ __global__ __launch_bounds__(kThreads) void adj_stress(AdjArgs<S, T> A) {
   if (tile_node(wk, i, j)) {
     const int64_t AP = A.aplane;
     const int64_t q = aidx(D, i, j);
-    T lo[9];
+    T lt[3], ln[6];
     bool any = false;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      lo[c] = A.X[(AL_T + c) * AP + q];
-      any |= lo[c] != T(0);
+      lt[c] = A.X[(AL_T + c) * AP + q];
+      any |= lt[c] != T(0);
     }
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
-      lo[3 + c] = A.X[(AL_N + c) * AP + q];
-      any |= lo[3 + c] != T(0);
+      ln[c] = A.X[(AL_N + c) * AP + q];
+      any |= ln[c] != T(0);
     }
     if (any) {
-      T in[13];
       int ci = i, cj = j;
       cmap(D, ci, cj);
       const int64_t qc = aidx(D, ci, cj);
+      T cc[3], g[3][2];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) in[c] = A.X[(AX_C + c) * AP + qc];
+      for (int c = 0; c < 3; ++c) cc[c] = A.X[(AX_C + c) * AP + qc];
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         T c9[9];
         c9_at(A.X, AP, D, i, j, k, c9);
-        grad9(c9, in[3 + 2 * k], in[4 + 2 * k]);
+        grad9(c9, g[k][0], g[k][1]);
       }
-      in[9] = A.X[(AX_C + 3) * AP + qc];
+      const T rho = A.X[(AX_C + 3) * AP + qc];
+      const T sig[3] = {(T)D.sig[0], (T)D.sig[1], (T)D.sig[2]};
+      T lc[3] = {0, 0, 0}, lg[3][2] = {{0, 0}, {0, 0}, {0, 0}}, lrho = T(0), lsig[3];
+      pair_stress_vjp(cc, g, rho, sig, A.eps_g, lt, ln, lc, lg, lrho, lsig);
 #pragma unroll
-      for (int c = 0; c < 3; ++c) in[10 + c] = (T)D.sig[c];
-#pragma unroll 1
-      for (int s = 0; s < 13; ++s) {
-        using DT = Dual<T>;
-        const DT cc[3] = {seeded(in[0], s, 0), seeded(in[1], s, 1), seeded(in[2], s, 2)};
-        DT g[3][2];
+      for (int c = 0; c < 3; ++c) aadd(&A.X[(AL_C + c) * AP + qc], lc[c]);
+      aadd(&A.X[(AL_C + 3) * AP + qc], lrho);
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          g[k][0] = seeded(in[3 + 2 * k], s, 3 + 2 * k);
-          g[k][1] = seeded(in[4 + 2 * k], s, 4 + 2 * k);
-        }
-        const DT rho = seeded(in[9], s, 9);
-        KT<DT> K = make_kt<DT>(D);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) K.sig[c] = seeded(in[10 + c], s, 10 + c);
-        DT txx, txy, tyy, nrm[6];
-        pair_stress(cc, g, rho, K, DT((double)A.eps_g), txx, txy, tyy, nrm);
-        T v = lo[0] * txx.d + lo[1] * txy.d + lo[2] * tyy.d;
-#pragma unroll
-        for (int c = 0; c < 6; ++c) v += lo[3 + c] * nrm[c].d;
-        if (s < 3) aadd(&A.X[(AL_C + s) * AP + qc], v);
-        else if (s < 9) A.X[(AL_G + s - 3) * AP + q] = v;
-        else if (s == 9) aadd(&A.X[(AL_C + 3) * AP + qc], v);
-        else sraw[s - 10] = (double)v;
+      for (int k = 0; k < 3; ++k) {
+        A.X[(AL_G + 2 * k) * AP + q] = lg[k][0];
+        A.X[(AL_G + 2 * k + 1) * AP + q] = lg[k][1];
       }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) sraw[c] = (double)lsig[c];
     }
   }
   block_add(sraw, A.raw + 9 * wk.dom);
@@ -580,27 +716,31 @@ __global__ __launch_bounds__(kThreads) void adj_comp(AdjArgs<S, T> A, int64_t tp
   o[2 * D.plane] = (l2 - m) * ir + lr;
 }
 
-// Adjoint of the wetting fill of one node: its filled C_1, C_2 (C_3 = 1 - C_1 - C_2) as
-// functions of the partial densities at the interpolation nodes of D0 and of the crossings of
-// its four lines, and of theta13, theta23, theta12.
-template <typename R>
-__device__ __forceinline__ R cfr(const R *r3, int k) { return r3[k] / (r3[0] + r3[1] + r3[2]); }
-
+// Adjoint of the wetting fill (Eq. 21-22), four lanes per fill node as in the forward fill: lane
+// `line` marches line `line` of fluid k = line / 2.  The filled C_1, C_2 (C_3 = 1 - C_1 - C_2)
+// depend on the partial densities at the interpolation nodes of D0 (through Eq. 21) and of the
+// chosen crossing (through the interpolation and, via the angle, the crossing's weight), and
+// on theta13, theta23, theta12.  The lane whose value Eq. 22 picked (the first lane of the
+// fluid when no line reached the fluid) carries that fluid's reverse-mode chain; its partials
+// are added atomically to the density adjoint and to the parameter partials.
 template <typename S, typename T>
 __global__ __launch_bounds__(kThreads) void adj_fill(AdjArgs<S, T> A, int64_t tplane) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= A.n_fill) return;
-  const FillNode fn = A.fill[idx];
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int idx = gid >> 2, line = gid & 3, k = line >> 1;
+  const bool active = idx < A.n_fill;
+  const FillNode fn = A.fill[active ? idx : 0];
   const DomainDev &D = A.doms[fn.dom];
   const int64_t AP = A.aplane;
-  const int64_t qa = aidx(D, fn.i, fn.j);
-  const double lC0 = (double)A.X[AL_C * AP + qa], lC1 = (double)A.X[(AL_C + 1) * AP + qa];
-  const double lC2 = (double)A.X[(AL_C + 2) * AP + qa];
-  const double lam1 = lC0 - lC2, lam2 = lC1 - lC2;
-  if (lam1 == 0.0 && lam2 == 0.0) return;
+  const int64_t P = D.plane;
   const uint8_t *flags = A.flags + D.base;
   const T *r = A.rin + 3 * D.base;
-  const int64_t P = D.plane;
+  T *lr = A.lout + 9 * tplane + 3 * D.base;
+  double lam = 0.0;  // adjoint of the filled C of fluid k
+  if (active) {
+    const int64_t qa = aidx(D, fn.i, fn.j);
+    lam = (double)A.X[(AL_C + k) * AP + qa] - (double)A.X[(AL_C + 2) * AP + qa];
+  }
+  const bool work = active && lam != 0.0;  // equal in the two lanes of a fluid
   auto fluid_at = [&](int i, int j) -> bool {
     const int dx = i - fn.i, dy = j - fn.j;
     if (dx >= -3 && dx <= 3 && dy >= -3 && dy <= 3) return (fn.mask >> ((dy + 3) * 7 + dx + 3)) & 1;
@@ -618,107 +758,108 @@ __global__ __launch_bounds__(kThreads) void adj_fill(AdjArgs<S, T> A, int64_t tp
     if (D.yper) j = wrap_small(j, D.ny);
     return plane_index(i, j, D.pitch);
   };
-  const double PI = 3.14159265358979323846;
-  // forward values in FP64 as the fill kernel forms them: angles and the lines' crossings
-  double rho_in[30];
-  int64_t node_of[10];
-  node_of[0] = fn.d0a;
-  node_of[1] = fn.d0b;
-  for (int c = 0; c < 3; ++c) {
-    rho_in[c] = (double)r[c * P + fn.d0a];
-    rho_in[3 + c] = (double)r[c * P + fn.d0b];
-  }
-  double Cb[3];
-  for (int k = 0; k < 3; ++k) {
-    const double ca = cfr(rho_in, k), cb = cfr(rho_in + 3, k);
-    Cb[k] = ca + fn.d0w * (cb - ca);
-  }
-  double thv[2];
-  {
-    const double a = fmax(Cb[1], 0.0), b = fmax(Cb[2], 0.0), den = a + b;
-    thv[0] = den > 1e-12 ? (b * D.th13 + a * D.th12) / den : 0.5 * (D.th13 + D.th12);
-    const double a2 = fmax(Cb[0], 0.0), den2 = a2 + b;
-    thv[1] = den2 > 1e-12 ? (b * D.th23 + a2 * (PI - D.th12)) / den2 : 0.5 * (D.th23 + PI - D.th12);
-  }
-  LineHit h[4];
-  for (int l = 0; l < 4; ++l) {
-    const int k = l >> 1;
-    const double tk = fmin(fmax(thv[k], 5.0 * PI / 180.0), 175.0 * PI / 180.0);
-    const double phi = fabs(0.5 * PI - tk);
-    double sp, cp;
-    sincos(phi, &sp, &cp);
-    if (l & 1) sp = -sp;
-    h[l] = march_line(fn.i, fn.j, cp * fn.nx + sp * (-fn.ny), cp * fn.ny + sp * fn.nx, fluid_at);
-    const int64_t n0 = h[l].ok ? node_q(h[l].i0, h[l].j0) : fn.d0a;
-    const int64_t n1 = h[l].ok ? node_q(h[l].i1, h[l].j1) : fn.d0a;
-    node_of[2 + 2 * l] = n0;
-    node_of[3 + 2 * l] = n1;
-    for (int c = 0; c < 3; ++c) {
-      rho_in[6 + 6 * l + c] = (double)r[c * P + n0];
-      rho_in[9 + 6 * l + c] = (double)r[c * P + n1];
+  const double PI = 3.14159265358979323846, LO = 5.0 * PI / 180.0, HI = 175.0 * PI / 180.0;
+  double Cb[3] = {0, 0, 0}, ra[3] = {0, 0, 0}, rb[3] = {0, 0, 0}, sa = 1, sb = 1;
+  double th = 0, tk = 0, wa = 0, wb = 0, den = 0, thA = 0, thB = 0;
+  double v = 0, w = 0, dw = 0, c0 = 0, c1 = 0, s0 = 1, s1 = 1;
+  int64_t n0 = 0, n1 = 0;
+  int ok = 0;
+  if (work) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      ra[q] = (double)r[q * P + fn.d0a];
+      rb[q] = (double)r[q * P + fn.d0b];
+    }
+    sa = ra[0] + ra[1] + ra[2];
+    sb = rb[0] + rb[1] + rb[2];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) Cb[q] = ra[q] / sa + fn.d0w * (rb[q] / sb - ra[q] / sa);
+    // Eq. (21): theta_k = (b thA + a thB) / (a + b), a and b the clipped C of the other fluids
+    thA = k == 0 ? D.th13 : D.th23;
+    thB = k == 0 ? D.th12 : PI - D.th12;
+    wa = fmax(Cb[k == 0 ? 1 : 0], 0.0);
+    wb = fmax(Cb[2], 0.0);
+    den = wa + wb;
+    th = den > 1e-12 ? (wb * thA + wa * thB) / den : 0.5 * (thA + thB);
+    tk = fmin(fmax(th, LO), HI);
+    const double ang = 0.5 * PI - tk, phi = fabs(ang);
+    double sn, cs;
+    sincos(phi, &sn, &cs);
+    const double sg = (line & 1) ? -1.0 : 1.0;
+    const double dx = cs * fn.nx - sg * sn * fn.ny, dy = cs * fn.ny + sg * sn * fn.nx;
+    const LineHit h = march_line(fn.i, fn.j, dx, dy, fluid_at);
+    if (h.ok) {
+      ok = 1;
+      n0 = node_q(h.i0, h.j0);
+      n1 = node_q(h.i1, h.j1);
+      s0 = (double)r[n0] + (double)r[P + n0] + (double)r[2 * P + n0];
+      s1 = (double)r[n1] + (double)r[P + n1] + (double)r[2 * P + n1];
+      c0 = (double)r[k * P + n0] / s0;
+      c1 = (double)r[k * P + n1] / s1;
+      w = h.w;
+      v = c0 + w * (c1 - c0);
+      // d w / d tk through the line direction (phi = |pi/2 - tk|)
+      const double ddx = -sn * fn.nx - sg * cs * fn.ny, ddy = -sn * fn.ny + sg * cs * fn.nx;
+      double dwdphi = 0.0;
+      if (h.i0 == h.i1 && h.j0 == h.j1) dwdphi = 0.0;  // through a node
+      else if (h.j0 == h.j1) dwdphi = (double)(h.j0 - fn.j) * (ddx * dy - dx * ddy) / (dy * dy);
+      else dwdphi = (double)(h.i0 - fn.i) * (ddy * dx - dy * ddx) / (dx * dx);
+      dw = dwdphi * (ang >= 0.0 ? -1.0 : 1.0);
     }
   }
-  double traw[3] = {0, 0, 0};
-  // one dual evaluation per input: 30 densities, theta13, theta23, theta12
-  for (int s = 0; s < 33; ++s) {
-    if (s >= 6 && s < 30 && !h[(s - 6) / 6].ok) continue;  // a line that failed reads nothing
-    using DD = Dual<double>;
-    DD rin_d[30];
-    for (int c = 0; c < 30; ++c) rin_d[c] = seeded(rho_in[c], s, c);
-    const DD t13 = seeded(D.th13, s, 30), t23 = seeded(D.th23, s, 31), t12 = seeded(D.th12, s, 32);
-    DD cb[3];
-    for (int k = 0; k < 3; ++k) {
-      const DD ca = cfr(rin_d, k), cbb = cfr(rin_d + 3, k);
-      cb[k] = ca + DD(fn.d0w) * (cbb - ca);
-    }
-    DD th[2];
-    {
-      const DD a = fmax(cb[1], DD(0.0)), b = fmax(cb[2], DD(0.0)), den = a + b;
-      th[0] = den.v > 1e-12 ? (b * t13 + a * t12) / den : DD(0.5) * (t13 + t12);
-      const DD a2 = fmax(cb[0], DD(0.0)), den2 = a2 + b;
-      const DD t21 = DD(PI) - t12;
-      th[1] = den2.v > 1e-12 ? (b * t23 + a2 * t21) / den2 : DD(0.5) * (t23 + t21);
-    }
-    DD v[4], tkk[2];
-    for (int l = 0; l < 4; ++l) {
-      const int k = l >> 1;
-      DD tk = th[k];
-      if (tk.v < 5.0 * PI / 180.0) tk = DD(5.0 * PI / 180.0);
-      if (tk.v > 175.0 * PI / 180.0) tk = DD(175.0 * PI / 180.0);
-      tkk[k] = tk;
-      if (!h[l].ok) continue;
-      const DD phi = fabs(DD(0.5 * PI) - tk);
-      DD sp, cp;
-      sincos_dual(phi, sp, cp);
-      if (l & 1) sp = -sp;
-      const DD dx = cp * DD(fn.nx) + sp * DD(-fn.ny), dy = cp * DD(fn.ny) + sp * DD(fn.nx);
-      DD w(0.0);
-      if (h[l].i0 == h[l].i1 && h[l].j0 == h[l].j1) {
-        w = DD(0.0);  // the line passes through a node
-      } else if (h[l].j0 == h[l].j1) {  // row y = j0 crossed at x = pi + (j0 - pj) dx / dy
-        w = DD((double)(fn.i - h[l].i0)) + DD((double)(h[l].j0 - fn.j)) * dx / dy;
-      } else {  // column x = i0 crossed at y = pj + (i0 - pi) dy / dx
-        w = DD((double)(fn.j - h[l].j0)) + DD((double)(h[l].i0 - fn.i)) * dy / dx;
-      }
-      const DD c0 = cfr(rin_d + 6 + 6 * l, k), c1 = cfr(rin_d + 9 + 6 * l, k);
-      v[l] = c0 + w * (c1 - c0);
-    }
-    DD cpk[2];
-    for (int k = 0; k < 2; ++k) {
-      const bool ok1 = h[2 * k].ok, ok2 = h[2 * k + 1].ok;
-      if (ok1 && ok2) cpk[k] = tkk[k].v <= 0.5 * PI ? fmax(v[2 * k], v[2 * k + 1]) : fmin(v[2 * k], v[2 * k + 1]);
-      else if (ok1) cpk[k] = v[2 * k];
-      else if (ok2) cpk[k] = v[2 * k + 1];
-      else cpk[k] = cb[k];
-    }
-    const double g = lam1 * cpk[0].d + lam2 * cpk[1].d;
-    if (g == 0.0) continue;
-    if (s < 30) aadd(&A.lout[9 * tplane + 3 * D.base + (s % 3) * P + node_of[s / 3]], (T)g);
-    else traw[s - 30] += g;
+  const double vo = __shfl_xor(v, 1);
+  const int oko = __shfl_xor(ok, 1);
+  const bool even = (line & 1) == 0;
+  bool chosen = ok != 0;
+  if (ok && oko) {  // Eq. (22): max for tk <= 90 degrees, min above; ties go to the first line
+    const double ve = even ? v : vo, vd = even ? vo : v;
+    const bool pick_even = tk <= 0.5 * PI ? ve >= vd : ve <= vd;
+    chosen = even == pick_even;
   }
-  // a work-group of fill nodes may span domains: one atomic per node and parameter
-  for (int c = 0; c < 3; ++c)
-    if (traw[c] != 0.0) aadd(&A.raw[9 * fn.dom + 6 + c], traw[c]);
+  const bool fallback = !ok && !oko;
+  if (!(work && (chosen || (fallback && even)))) return;
+  double lCb[3] = {0, 0, 0}, ltk = 0.0;
+  if (fallback) {
+    lCb[k] = lam;
+  } else {
+    const double l0 = lam * (1.0 - w), l1 = lam * w;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const double g0 = l0 * ((q == k ? 1.0 : 0.0) - c0) / s0;
+      if (g0 != 0.0) aadd(lr + q * P + n0, (T)g0);
+      const double g1 = l1 * ((q == k ? 1.0 : 0.0) - c1) / s1;
+      if (g1 != 0.0) aadd(lr + q * P + n1, (T)g1);
+    }
+    ltk = lam * (c1 - c0) * dw;
+  }
+  const double lth = (th >= LO && th <= HI) ? ltk : 0.0;
+  double lA = 0.0, lB = 0.0;
+  if (den > 1e-12) {
+    lA = lth * wb / den;
+    lB = lth * wa / den;
+    const double la = lth * (thB - th) / den, lb = lth * (thA - th) / den;
+    if (Cb[k == 0 ? 1 : 0] >= 0.0) lCb[k == 0 ? 1 : 0] += la;
+    if (Cb[2] >= 0.0) lCb[2] += lb;
+  } else {
+    lA = 0.5 * lth;
+    lB = 0.5 * lth;
+  }
+  // C at D0 = C(d0a) + d0w (C(d0b) - C(d0a)), C(x) = rho_k(x) / sum rho(x)
+  double ma = 0.0, mb = 0.0;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    ma += lCb[q] * (1.0 - fn.d0w) * ra[q] / sa;
+    mb += lCb[q] * fn.d0w * rb[q] / sb;
+  }
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const double ga = (lCb[q] * (1.0 - fn.d0w) - ma) / sa, gb = (lCb[q] * fn.d0w - mb) / sb;
+    if (ga != 0.0) aadd(lr + q * P + fn.d0a, (T)ga);
+    if (gb != 0.0) aadd(lr + q * P + fn.d0b, (T)gb);
+  }
+  // theta12 enters fluid 2's angle as theta21 = pi - theta12
+  if (lA != 0.0) aadd(&A.raw[9 * fn.dom + 6 + k], lA);
+  if (lB != 0.0) aadd(&A.raw[9 * fn.dom + 8], k == 0 ? lB : -lB);
 }
 
 // Seed: lambda_rho_k = dL/drho_k of a loss of the partial densities at fluid nodes, read from a
@@ -752,7 +893,7 @@ hipError_t launch_adjoint(const AdjArgs<S, T> &a, int64_t tplane, hipStream_t s)
   hipLaunchKernelGGL((adj_grad<S, T>), g, b, 0, s, a);
   hipLaunchKernelGGL((adj_comp<S, T>), g, b, 0, s, a, tplane);
   if (a.n_fill > 0)
-    hipLaunchKernelGGL((adj_fill<S, T>), dim3((a.n_fill + kThreads - 1) / kThreads), b, 0, s, a, tplane);
+    hipLaunchKernelGGL((adj_fill<S, T>), dim3((4 * a.n_fill + kThreads - 1) / kThreads), b, 0, s, a, tplane);
   return hipGetLastError();
 }
 

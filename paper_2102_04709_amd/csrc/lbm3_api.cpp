@@ -710,6 +710,26 @@ lbm3_status adjoint_step_t(lbm3_ctx *c, const void *state, const void *lin, void
   return LBM3_OK;
 }
 
+// Back-to-back launches on the current state: n wetting fills, then n fused steps that all
+// compute the same next state into the other buffer (the state does not advance).
+template <typename S, typename T>
+lbm3_status time_kernels_t(lbm3_ctx *c, int n, hipEvent_t ev[3]) {
+  hipStream_t s = c->stream;
+  const int nw = (int)c->work.size();
+  const bool persistent = c->persistent > 0;
+  const int grid = persistent ? std::min(c->persistent, nw) : round_up(nw, 8);
+  StepArgs<S, T> a = step_args<S, T>(c, c->cur);
+  a.remap = persistent ? 0 : 1;
+  const FillArgs<T> f = fill_args<T>(c, c->cur);
+  HIPC(c, launch_fill<T>(f, s));
+  HIPC(c, hipEventRecord(ev[0], s));
+  for (int k = 0; k < n; ++k) HIPC(c, launch_fill<T>(f, s));
+  HIPC(c, hipEventRecord(ev[1], s));
+  for (int k = 0; k < n; ++k) HIPC(c, (launch_step<S, T>(a, grid, c->mode, false, s)));
+  HIPC(c, hipEventRecord(ev[2], s));
+  return LBM3_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1014,25 +1034,24 @@ lbm3_status lbm3_adjoint_grad(lbm3_ctx *c, double *host_grad) {
 
 lbm3_status lbm3_kernel_times(lbm3_ctx *c, int32_t nsteps, double *ms_fill, double *ms_step) {
   if (!c || nsteps < 1 || !ms_step || !ms_fill) return LBM3_EINVAL;
-  std::vector<hipEvent_t> ev(3 * nsteps, nullptr);
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
   for (auto &e : ev) HIPC(c, hipEventCreate(&e));
-  lbm3_status st = enqueue_steps(c, nsteps, c->stream, ev.data());
-  double tf = 0, ts = 0;
+  lbm3_status st;
+  switch (c->precision) {
+    case LBM3_F64: st = time_kernels_t<double, double>(c, nsteps, ev); break;
+    case LBM3_F32: st = time_kernels_t<float, float>(c, nsteps, ev); break;
+    default: st = time_kernels_t<__half, float>(c, nsteps, ev); break;
+  }
+  float a = 0, b = 0;
   if (st == LBM3_OK) {
-    hipError_t e = hipEventSynchronize(ev.back());
+    hipError_t e = hipEventSynchronize(ev[2]);
     if (e != hipSuccess) st = hip_fail(c, e, "hipEventSynchronize");
-    for (int k = 0; k < nsteps && st == LBM3_OK; ++k) {
-      float a = 0, b = 0;
-      (void)hipEventElapsedTime(&a, ev[3 * k], ev[3 * k + 1]);
-      (void)hipEventElapsedTime(&b, ev[3 * k + 1], ev[3 * k + 2]);
-      tf += a;
-      ts += b;
-    }
-    c->steps += nsteps;
+    (void)hipEventElapsedTime(&a, ev[0], ev[1]);
+    (void)hipEventElapsedTime(&b, ev[1], ev[2]);
   }
   for (auto &e : ev) (void)hipEventDestroy(e);
-  *ms_fill = tf / nsteps;
-  *ms_step = ts / nsteps;
+  *ms_fill = a / nsteps;
+  *ms_step = b / nsteps;
   return st;
 }
 

@@ -207,15 +207,43 @@ def pillar_sweep(n_domains=96, base_seed=2102_000) -> List[Workload]:
 
 
 def inverse_problem(hidden=False) -> Workload:
-    """512 x 256 domain with 12 pillars (seed 4709) and the compound droplet.  hidden=True
-    gives the parameters that produce the target phase fields, otherwise the point at which
-    gradients are taken."""
+    """The inverse problem: a 512 x 256 channel (periodic in y, Zou-He inlet u = 0.005 at x = 0,
+    outlet rho = 1 at x = nx-1) with 12 random pillars (seed 4709; radii 8..24, gap 4, 8
+    columns from the inlet and outlet) and the compound droplet of the sweep (core fluid 1 of
+    radius 15 inside a shell of fluid 2 of radius 25) resting against the upstream side of a
+    pillar, its centre 13 nodes from the pillar surface, so that both fluids touch the solid from
+    the first step and the contact angles shape the phase fields.  The host pillar is the first
+    one (in drawing order) with room for the droplet (2 nodes clear of every other pillar, 12
+    columns from the inlet, inside the periodic strip).  hidden=True gives the parameters that
+    produce the target phase fields, otherwise the point at which gradients are taken."""
     if hidden:
         theta, sigma = (40.0, 110.0), (0.020, 0.012, 0.010)
     else:
         theta, sigma = (50.0, 100.0), (0.018, 0.011, 0.011)
-    return pillar_domain(4709, nx=512, ny=256, n_pillars=12, theta=theta, sigma=sigma,
-                         name="inverse_hidden" if hidden else "inverse_guess")
+    nx, ny, r_core, r_shell, gap_core = 512, 256, 15.0, 25.0, 13.0
+    rng = np.random.Generator(np.random.PCG64(4709))
+    pillars = _place_pillars(rng, nx, ny, 12, 8.0, 24.0, (-1e9, -1e9), 0.0, 4.0, 8.0)
+    drop = None
+    for cx, cy, r in pillars:
+        dx, dy = cx - r - gap_core, cy
+        if dx - r_shell < 12.0 or dy - r_shell < 2.0 or dy + r_shell > ny - 3.0:
+            continue
+        if any(math.hypot(dx - px, dy - py) < pr + r_shell + 2.0
+               for px, py, pr in pillars if (px, py, pr) != (cx, cy, r)):
+            continue
+        drop = (dx, dy)
+        break
+    assert drop is not None
+    x, y = _grid(nx, ny)
+    solid = np.zeros((ny, nx), np.uint8)
+    for cx, cy, r in pillars:
+        solid |= _solid_disk(x, y, cx, cy, r).astype(np.uint8)
+    m1 = _disk(x, y, drop[0], drop[1], r_core)
+    m2 = _disk(x, y, drop[0], drop[1], r_shell)
+    nu = (1 / 6, 1 / 6, 1 / 6)
+    return Workload("inverse_hidden" if hidden else "inverse_guess", nx, ny, 1, BC_ZOUHE, nu, sigma, theta,
+                    solid, _phases([m1, m2], solid), circles=np.array(pillars, dtype=np.float64).reshape(-1, 3),
+                    u_in=0.005, rho_out=1.0)
 
 
 # ---- small cases used by tests ------------------------------------------------------------

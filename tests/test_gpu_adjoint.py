@@ -138,7 +138,7 @@ def test_adjoint_of_state_directional():
     torch, lbm3, rollout = _mods()
     w = W.random_mixture(64, 40, 21, walls=True, circles=[(33.2, 20.4, 6.8)])
     steps = 10
-    target = oracle_C(w.with_params(theta_deg=(50.0, 115.0)), steps)
+    target = oracle_C(w.with_params(theta_deg=(55.0, 105.0)), steps)
     sim = lbm3.Simulation(w, precision="f64", adjoint=True)
     s0 = sim.get_state()
     fl = torch.as_tensor(w.solid == 0, device=s0.device)
