@@ -47,6 +47,7 @@ struct AdjArgs {
   T *lout;          // adjoint of the state at t, 12 planes in the state layout
   double *raw;      // [9 n_dom] raw parameter partials
   T eps_g;
+  T eps_n;          // |G| below which the adjoint treats a pair normal as constant
 };
 
 // The adjoint of one step (every kernel, in order).  tplane = elements of one state plane summed

@@ -563,10 +563,11 @@ __global__ __launch_bounds__(kThreads) void adj_div(AdjArgs<S, T> A) {
 // Reverse-mode product of pair_stress (Eq. 10 with the normals of Eq. 13): given the adjoints of
 // the stress (lt[3]) and of the pair normals (ln[6]), accumulates the adjoints of C[3], of the
 // colour gradients g[3][2], of rho and of the tensions sigma[3].
+// Where |G_kl| < eps_n the normal is treated as locally constant (its derivative dropped).
 template <typename T>
 __device__ __forceinline__ void pair_stress_vjp(const T cc[3], const T g[3][2], T rho, const T sig[3], T eps,
-                                                const T lt[3], const T ln[6], T lc[3], T lg[3][2], T &lrho,
-                                                T lsig[3]) {
+                                                T eps_n, const T lt[3], const T ln[6], T lc[3], T lg[3][2],
+                                                T &lrho, T lsig[3]) {
   const int pk[3] = {0, 0, 1}, pl[3] = {1, 2, 2};
 #pragma unroll
   for (int pr = 0; pr < 3; ++pr) {
@@ -593,8 +594,10 @@ __device__ __forceinline__ void pair_stress_vjp(const T cc[3], const T g[3][2], 
     // n = G / |G|: lG += (ln - n (n . ln)) / |G|
     const T lnx = ln[2 * pr], lny = ln[2 * pr + 1];
     const T nl = nx * lnx + ny * lny;
-    lGx += (lnx - nx * nl) * im;
-    lGy += (lny - ny * nl) * im;
+    if (mag > eps_n) {
+      lGx += (lnx - nx * nl) * im;
+      lGy += (lny - ny * nl) * im;
+    }
     lsig[pr] = lS * Akl;
     const T lQ = (Q >= T(0) && Q <= T(1)) ? lS * sig[pr] : T(0);
     const T lrk = T(1e6) * rl * lQ, lrl = T(1e6) * rk * lQ;
@@ -649,7 +652,7 @@ __global__ __launch_bounds__(kThreads) void adj_stress(AdjArgs<S, T> A) {
       const T rho = A.X[(AX_C + 3) * AP + qc];
       const T sig[3] = {(T)D.sig[0], (T)D.sig[1], (T)D.sig[2]};
       T lc[3] = {0, 0, 0}, lg[3][2] = {{0, 0}, {0, 0}, {0, 0}}, lrho = T(0), lsig[3];
-      pair_stress_vjp(cc, g, rho, sig, A.eps_g, lt, ln, lc, lg, lrho, lsig);
+      pair_stress_vjp(cc, g, rho, sig, A.eps_g, A.eps_n, lt, ln, lc, lg, lrho, lsig);
 #pragma unroll
       for (int c = 0; c < 3; ++c) aadd(&A.X[(AL_C + c) * AP + qc], lc[c]);
       aadd(&A.X[(AL_C + 3) * AP + qc], lrho);

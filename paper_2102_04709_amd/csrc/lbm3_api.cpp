@@ -44,6 +44,16 @@ const Candidate kCands[] = {{MODE_TILE, 32, 8},     {MODE_TILE, 16, 16},    {MOD
 const int kMinTileArea = 256;
 const int kMinStripRows = 8;
 const int kFieldTileX = 32, kFieldTileY = 8;  // tile of the field export
+// |G_kl| at or below which n_kl := 0 and the pair adds no stress, in every precision (|G|^2 =
+// 1e-24 is still a normal FP32 number; a larger FP32 threshold switches normals on and off where
+// FP64 keeps them and lets the FP32 path drift from the FP64 one near walls).
+const double kEpsG = 1e-12;
+// The FP32 adjoint treats n_kl as constant where |G_kl| < 1e-8: below that |G| is smaller than
+// the FP32 rounding of the two products it is formed from, and the 1/|G| of the normal's
+// derivative feeds rounding noise into a mode of the adjoint that then grows without bound
+// (overflow within ~700 steps on the 512 x 256 inverse problem at a cutoff of 1e-10).  The FP64
+// adjoint is exact.
+const double kEpsNormalAdjF32 = 1e-8;
 const int kAdjTileX = 32, kAdjTileY = 8;      // tile of the adjoint kernels
 
 int round_up(int v, int m) { return (v + m - 1) / m * m; }
@@ -551,7 +561,7 @@ StepArgs<S, T> step_args(lbm3_ctx *c, int from) {
   a.rout = c->at<T>(c->L.off_R[1 - from]);
   a.tile_x = c->tx;
   a.tile_y = c->ty;
-  a.eps_g = sizeof(T) == 8 ? T(1e-12) : T(1e-7);
+  a.eps_g = T(kEpsG);
   a.out_rho = a.out_u = a.out_force = nullptr;
   return a;
 }
@@ -705,7 +715,8 @@ lbm3_status adjoint_step_t(lbm3_ctx *c, const void *state, const void *lin, void
   a.lin = reinterpret_cast<const T *>(lin);
   a.lout = reinterpret_cast<T *>(lout);
   a.raw = c->at<double>(c->L.off_raw);
-  a.eps_g = sizeof(T) == 8 ? T(1e-12) : T(1e-7);
+  a.eps_g = T(kEpsG);
+  a.eps_n = sizeof(T) == 8 ? T(kEpsG) : T(kEpsNormalAdjF32);
   HIPC(c, (launch_adjoint<S, T>(a, c->L.total_plane, c->stream)));
   return LBM3_OK;
 }
