@@ -20,13 +20,11 @@ enum {
   AX_N = 7,      // 6: pair normals
   AX_F = 13,     // 2: interfacial force
   AX_P = 15,     // 13: post-collision shifted f (9), R (4)
-  AL_P = 28,     // 13: adjoint of the post-collision data
-  AL_F = 41,     // 2: adjoint of F
-  AL_N = 43,     // 6: adjoint of n
-  AL_T = 49,     // 3: adjoint of the stress
-  AL_G = 52,     // 6: adjoint of the colour gradients
-  AL_C = 58,     // 4: adjoint of C_k and rho
-  A_PLANES = 62
+  AL_F = 28,     // 2: adjoint of F (fluid nodes)
+  AL_N = 30,     // 6: adjoint of n (fluid nodes)
+  AL_G = 36,     // 6: adjoint of the colour gradients
+  AL_C = 42,     // 4: adjoint of C_k and rho
+  A_PLANES = 46
 };
 
 template <typename S, typename T>

@@ -7,10 +7,11 @@
 // Forward intermediates of s_t (on an extended grid, see lbm3_adjoint.h): C_k and rho with the
 // filled C at the solid boundary nodes (Eq. 21-22), stress and pair normals (Eq. 10, 12),
 // interfacial force, post-collision f' and recolouring vectors R (Eq. 1-9, 11, 13-15).
-// Transposes, in reverse order of the forward: streaming (Eq. 16 with every boundary rule, as
-// atomic scatters), the per-node collision + recolouring and the per-position stress (reverse-
-// mode products written out from the forward formulas), the stress divergence, the colour-
-// gradient stencil, the mass fractions, and the wetting fill (its discrete choices -- which
+// Transposes, in reverse order of the forward: streaming (Eq. 16 with every boundary rule, in
+// gather form) with the per-node collision + recolouring, the stress divergence (gathered) with
+// the per-position stress (reverse-mode products written out from the forward formulas), the
+// colour-gradient stencil (atomic scatter), the mass fractions, and the wetting fill (its
+// discrete choices -- which
 // crossing, which line -- fixed at their forward values).  Non-smooth points (the max/min of
 // Eq. 22, clamps, the |G| threshold) take the derivative of the branch the forward took: a
 // clamp passes the derivative when its argument lies inside or on the bounds, max/min give it
@@ -183,13 +184,6 @@ __global__ __launch_bounds__(kThreads) void adj_fwd_p(AdjArgs<S, T> A) {
   for (int c = 0; c < 4; ++c) XP(A.X, AP, AX_P + 9 + c, q) = Rv[c];
 }
 
-template <typename S, typename T>
-__global__ __launch_bounds__(kThreads) void adj_zero(AdjArgs<S, T> A, int64_t n) {
-  T *p = A.X + (int64_t)AL_P * A.aplane;
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
-    p[k] = T(0);
-}
-
 // ---- transposes ----------------------------------------------------------------------------
 // Zou-He at a boundary node y (Eq. 16 with the Zou-He rule): the unknown totals are affine in
 // the known ones, so the adjoint of a known population d of y gains a term from the adjoints of
@@ -235,13 +229,11 @@ __device__ __forceinline__ T zh_add(const DomainDev &D, bool inlet, int d, const
 //   - the same y, when its link opposite to d is cut with q < 1/2 and x + 2 e_d is solid, reads
 //     f'_d(x) again with weight 1 - 2q (interpolated bounce-back);
 //   - x itself, for each of its own solid links (halfway or interpolated bounce-back).
-// No atomics: every adjoint of x's data is written by x's thread.
+// No atomics: every adjoint of x's data is written by x's thread, which then applies the
+// collision transpose to them at once (adj_node).
 template <typename S, typename T>
-__global__ __launch_bounds__(kThreads) void adj_stream(AdjArgs<S, T> A, int64_t tplane) {
-  const WorkItem wk = A.work[blockIdx.x];
-  const DomainDev &D = A.doms[wk.dom];
-  int i, j;
-  if (!tile_node(wk, i, j) || !fluid_node(A.flags, D, i, j)) return;
+__device__ __forceinline__ void stream_gather(const AdjArgs<S, T> &A, const DomainDev &D, int i, int j, int64_t tplane,
+                                              T lP[13], T lC[3]) {
   const int64_t AP = A.aplane;
   const int64_t P = D.plane;
   const int64_t li = plane_index(i, j, D.pitch);
@@ -253,9 +245,10 @@ __global__ __launch_bounds__(kThreads) void adj_stream(AdjArgs<S, T> A, int64_t 
   T fp[9];
 #pragma unroll
   for (int a = 0; a < 9; ++a) fp[a] = A.X[(AX_P + a) * AP + q];
-  T lP[13], lC[3] = {T(0), T(0), T(0)};
 #pragma unroll
   for (int c = 0; c < 13; ++c) lP[c] = T(0);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) lC[c] = T(0);
   // a read of f'_dir(x) with weight coef into a node whose total has adjoint lfv and whose
   // partial densities have adjoints m[3] (the recoloured part k is C_k (f' + w) + w R_k.e)
   auto take = [&](int dir, T coef, T lfv, T m0, T m1, T m2) {
@@ -352,10 +345,6 @@ __global__ __launch_bounds__(kThreads) void adj_stream(AdjArgs<S, T> A, int64_t 
     lC[1] += mu1 * su;
     lC[2] += mu2 * su;
   }
-#pragma unroll
-  for (int c = 0; c < 13; ++c) A.X[(AL_P + c) * AP + q] = lP[c];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) A.X[(AL_C + c) * AP + q] = lC[c];
 }
 
 // Reverse-mode product of collide_shifted (Eq. 1-9, 11) followed by recolour_R (Eq. 13-15):
@@ -495,69 +484,50 @@ __device__ __forceinline__ void collide_recolour_vjp(const T f[9], T Fxi, T Fyi,
   lrt = lr0 * C[0] + lr1 * C[1] + lr2 * C[2] - lirt * irt * irt;
 }
 
-// Adjoint of the per-node collision and recolouring.
+// Adjoint of streaming and of the per-node collision and recolouring, node by node.  At solid
+// positions of the grid it clears the adjoint of C (the stress and stencil transposes add there).
 template <typename S, typename T>
-__global__ __launch_bounds__(kThreads) void adj_collide(AdjArgs<S, T> A) {
+__global__ __launch_bounds__(kThreads) void adj_node(AdjArgs<S, T> A, int64_t tplane) {
   const WorkItem wk = A.work[blockIdx.x];
   const DomainDev &D = A.doms[wk.dom];
   int i, j;
   double graw[3] = {0, 0, 0};
-  if (tile_node(wk, i, j) && fluid_node(A.flags, D, i, j)) {
-    const int64_t AP = A.aplane;
-    const int64_t li = plane_index(i, j, D.pitch);
+  const int64_t AP = A.aplane;
+  if (tile_node(wk, i, j) && i >= 0 && i < D.nx) {
     const int64_t q = aidx(D, i, j);
-    const KT<T> K = make_kt<T>(D);
-    T f[9], C[3], nrm[6], lfd[9], lR[4];
+    if (!fluid_node(A.flags, D, i, j)) {
 #pragma unroll
-    for (int a = 0; a < 9; ++a) f[a] = load_s<S, T>(A.fin + 9 * D.base + a * D.plane + li);
+      for (int c = 0; c < 4; ++c) A.X[(AL_C + c) * AP + q] = T(0);
+    } else {
+      T lP[13], lCs[3];
+      stream_gather(A, D, i, j, tplane, lP, lCs);
+      const int64_t li = plane_index(i, j, D.pitch);
+      const KT<T> K = make_kt<T>(D);
+      T f[9], C[3], nrm[6];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) C[c] = A.X[(AX_C + c) * AP + q];
-    const T rt = A.X[(AX_C + 3) * AP + q];
+      for (int a = 0; a < 9; ++a) f[a] = load_s<S, T>(A.fin + 9 * D.base + a * D.plane + li);
 #pragma unroll
-    for (int c = 0; c < 6; ++c) nrm[c] = A.X[(AX_N + c) * AP + q];
+      for (int c = 0; c < 3; ++c) C[c] = A.X[(AX_C + c) * AP + q];
+      const T rt = A.X[(AX_C + 3) * AP + q];
 #pragma unroll
-    for (int a = 0; a < 9; ++a) lfd[a] = A.X[(AL_P + a) * AP + q];
+      for (int c = 0; c < 6; ++c) nrm[c] = A.X[(AX_N + c) * AP + q];
+      T lf[9], lFx, lFy, lC[3], lrt, ln[6], lgX[3];
+      collide_recolour_vjp(f, A.X[AX_F * AP + q], A.X[(AX_F + 1) * AP + q], C, rt, nrm, K, lP, lP + 9, lf, lFx, lFy,
+                           lC, lrt, ln, lgX);
 #pragma unroll
-    for (int c = 0; c < 4; ++c) lR[c] = A.X[(AL_P + 9 + c) * AP + q];
-    T lf[9], lFx, lFy, lC[3], lrt, ln[6], lgX[3];
-    collide_recolour_vjp(f, A.X[AX_F * AP + q], A.X[(AX_F + 1) * AP + q], C, rt, nrm, K, lfd, lR, lf, lFx, lFy,
-                         lC, lrt, ln, lgX);
+      for (int a = 0; a < 9; ++a) A.lout[9 * D.base + a * D.plane + li] = lf[a];
+      A.X[AL_F * AP + q] = lFx;
+      A.X[(AL_F + 1) * AP + q] = lFy;
 #pragma unroll
-    for (int a = 0; a < 9; ++a) A.lout[9 * D.base + a * D.plane + li] = lf[a];
-    A.X[AL_F * AP + q] = lFx;
-    A.X[(AL_F + 1) * AP + q] = lFy;
+      for (int c = 0; c < 3; ++c) A.X[(AL_C + c) * AP + q] = lC[c] + lCs[c];
+      A.X[(AL_C + 3) * AP + q] = lrt;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) A.X[(AL_C + c) * AP + q] += lC[c];
-    A.X[(AL_C + 3) * AP + q] += lrt;
+      for (int c = 0; c < 6; ++c) A.X[(AL_N + c) * AP + q] = ln[c];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) A.X[(AL_N + c) * AP + q] = ln[c];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) graw[c] = (double)lgX[c];
+      for (int c = 0; c < 3; ++c) graw[c] = (double)lgX[c];
+    }
   }
   block_add(graw, A.raw + 9 * wk.dom + 3);
-}
-
-// Adjoint of the stress divergence F(x) = 3 sum_a w_a T(x + e_a) . e_a (Eq. 12 on Eq. 10).
-template <typename S, typename T>
-__global__ __launch_bounds__(kThreads) void adj_div(AdjArgs<S, T> A) {
-  const WorkItem wk = A.work[blockIdx.x];
-  const DomainDev &D = A.doms[wk.dom];
-  int i, j;
-  if (!tile_node(wk, i, j) || !fluid_node(A.flags, D, i, j)) return;
-  const int64_t AP = A.aplane;
-  const int64_t q = aidx(D, i, j);
-  const T lx = A.X[AL_F * AP + q], ly = A.X[(AL_F + 1) * AP + q];
-#pragma unroll
-  for (int a = 1; a < 9; ++a) {
-    const int ex = lat_ex(a), ey = lat_ey(a);
-    int ii = i + ex, jj = j + ey;
-    tmap(D, ii, jj);
-    const int64_t z = aidx(D, ii, jj);
-    const T c = T(3) * wgt<T>(a);
-    if (ex) aadd(&A.X[AL_T * AP + z], c * T(ex) * lx);
-    aadd(&A.X[(AL_T + 1) * AP + z], c * (T(ey) * lx + T(ex) * ly));
-    if (ey) aadd(&A.X[(AL_T + 2) * AP + z], c * T(ey) * ly);
-  }
 }
 
 // Reverse-mode product of pair_stress (Eq. 10 with the normals of Eq. 13): given the adjoints of
@@ -614,7 +584,10 @@ __device__ __forceinline__ void pair_stress_vjp(const T cc[3], const T g[3][2], 
   }
 }
 
-// Adjoint of the per-position stress and normals.
+// Adjoint of the stress divergence and of the per-position stress and normals.  The stress at
+// position z is read by the divergence F(y) = 3 sum_a w_a T(y + e_a) . e_a (Eq. 12 on Eq. 10)
+// of the fluid nodes y = z - e_a (periodic axes wrap, other axes do not), so the adjoint of the
+// stress at z is gathered from their adjoint forces; the normals at z matter only at fluid nodes.
 template <typename S, typename T>
 __global__ __launch_bounds__(kThreads) void adj_stress(AdjArgs<S, T> A) {
   const WorkItem wk = A.work[blockIdx.x];
@@ -624,19 +597,33 @@ __global__ __launch_bounds__(kThreads) void adj_stress(AdjArgs<S, T> A) {
   if (tile_node(wk, i, j)) {
     const int64_t AP = A.aplane;
     const int64_t q = aidx(D, i, j);
-    T lt[3], ln[6];
+    T lt[3] = {T(0), T(0), T(0)}, ln[6];
+#pragma unroll
+    for (int a = 1; a < 9; ++a) {
+      const int ex = lat_ex(a), ey = lat_ey(a);
+      int yi = i - ex, yj = j - ey;
+      if (D.bcx != BCX_ZOUHE) yi = wrap_small(yi, D.nx);
+      if (D.yper) yj = wrap_small(yj, D.ny);
+      if (!fluid_node(A.flags, D, yi, yj)) continue;
+      const int64_t y = aidx(D, yi, yj);
+      const T lx = A.X[AL_F * AP + y], ly = A.X[(AL_F + 1) * AP + y];
+      const T c = T(3) * wgt<T>(a);
+      lt[0] += c * T(ex) * lx;
+      lt[1] += c * (T(ey) * lx + T(ex) * ly);
+      lt[2] += c * T(ey) * ly;
+    }
+    const bool fluid = fluid_node(A.flags, D, i, j);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) ln[c] = fluid ? A.X[(AL_N + c) * AP + q] : T(0);
     bool any = false;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      lt[c] = A.X[(AL_T + c) * AP + q];
-      any |= lt[c] != T(0);
-    }
+    for (int c = 0; c < 3; ++c) any |= lt[c] != T(0);
 #pragma unroll
-    for (int c = 0; c < 6; ++c) {
-      ln[c] = A.X[(AL_N + c) * AP + q];
-      any |= ln[c] != T(0);
-    }
-    if (any) {
+    for (int c = 0; c < 6; ++c) any |= ln[c] != T(0);
+    if (!any) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) A.X[(AL_G + c) * AP + q] = T(0);
+    } else {
       int ci = i, cj = j;
       cmap(D, ci, cj);
       const int64_t qc = aidx(D, ci, cj);
@@ -887,11 +874,7 @@ hipError_t launch_adjoint(const AdjArgs<S, T> &a, int64_t tplane, hipStream_t s)
   hipLaunchKernelGGL((adj_fwd_c<S, T>), g, b, 0, s, a);
   hipLaunchKernelGGL((adj_fwd_t<S, T>), g, b, 0, s, a);
   hipLaunchKernelGGL((adj_fwd_p<S, T>), g, b, 0, s, a);
-  const int64_t nz = (int64_t)(A_PLANES - AL_P) * a.aplane;
-  hipLaunchKernelGGL((adj_zero<S, T>), dim3(1024), b, 0, s, a, nz);
-  hipLaunchKernelGGL((adj_stream<S, T>), g, b, 0, s, a, tplane);
-  hipLaunchKernelGGL((adj_collide<S, T>), g, b, 0, s, a);
-  hipLaunchKernelGGL((adj_div<S, T>), g, b, 0, s, a);
+  hipLaunchKernelGGL((adj_node<S, T>), g, b, 0, s, a, tplane);
   hipLaunchKernelGGL((adj_stress<S, T>), g, b, 0, s, a);
   hipLaunchKernelGGL((adj_grad<S, T>), g, b, 0, s, a);
   hipLaunchKernelGGL((adj_comp<S, T>), g, b, 0, s, a, tplane);
