@@ -545,12 +545,11 @@ __device__ __forceinline__ void pair_stress_vjp(const T cc[3], const T g[3][2], 
     lsig[pr] = T(0);
     const T Gx = cc[l] * g[k][0] - cc[k] * g[l][0];
     const T Gy = cc[l] * g[k][1] - cc[k] * g[l][1];
-    const T mag = sqrt(Gx * Gx + Gy * Gy);
-    if (!(mag > eps)) continue;  // stress and normal are the constant zero there
+    T mag, im;
+    if (!pair_norm(Gx, Gy, eps, mag, im)) continue;  // stress and normal are zero there
     const T rk = cc[k] * rho, rl = cc[l] * rho;
     const T Q = T(1e6) * rk * rl;
     const T Akl = fmin(fmax(Q, T(0)), T(1));
-    const T im = rcp(mag);
     const T nx = Gx * im, ny = Gy * im;
     const T S = sig[pr] * Akl;
     // T_pair = S (Gy^2, -Gx Gy, Gx^2) / |G|

@@ -1,8 +1,8 @@
 // lbm3_device.h -- per-node device code of liblbm3 shared by the forward kernels and the adjoint
 // kernels (lattice constants, storage conversions, node indexing, the wetting fill of one node,
 // the colour-gradient stress, the MRT collision with forcing, the recolouring vectors and the
-// pull-streaming of one node).  Every function is a template on the arithmetic type so that the
-// adjoint can evaluate the same code on dual numbers.
+// pull-streaming of one node).  Every function is a template on the arithmetic type (FP64 or
+// FP32); the adjoint recomputes its forward intermediates with the same functions.
 #pragma once
 
 #include <hip/hip_fp16.h>
@@ -69,11 +69,10 @@ __device__ __forceinline__ int64_t node_index(int gx, int gy, const DomainDev &D
 }
 
 // ------------------------------------------------------------------------------------------
-// Wetting fill, Eq. (19)-(22), of one solid boundary node, computed where it is needed: the
-// fused kernels call it for every fill node in the halo they load, so the filled C never goes
-// through HBM.  All geometry is FP64; C at fluid nodes is rho_k / rho of the stored densities.
-// The march tests fluid nodes with the node's 7 x 7 fluid mask and reads the flag plane only
-// beyond it.
+// Wetting fill, Eq. (19)-(22), of one solid boundary node (the wet_fill kernel runs it for every
+// fill node once per step and writes the filled C to a compact array).  All geometry is FP64; C
+// at fluid nodes is rho_k / rho of the stored densities.  The march tests fluid nodes with the
+// node's 7 x 7 fluid mask and reads the flag plane only beyond it.
 template <typename T>
 __device__ __forceinline__ double cfrac_at(const T *r, int64_t P, int64_t q, int k) {
   const double a = (double)r[q], b = (double)r[P + q], d = (double)r[2 * P + q];
@@ -211,6 +210,22 @@ __device__ __forceinline__ void grad9(const T *c, T &gx, T &gy) {
   gy = T(1.0 / 3.0) * (c[2] - c[4]) + T(1.0 / 12.0) * (c[5] + c[6] - c[7] - c[8]);
 }
 
+// |G| and 1/|G| of a colour-gradient difference, when |G| > eps (else false): the hardware
+// reciprocal square root (1 ulp) in FP32, an IEEE square root and division in FP64.
+__device__ __forceinline__ bool pair_norm(float gx, float gy, float eps, float &mag, float &im) {
+  const float s2 = gx * gx + gy * gy;
+  if (!(s2 > eps * eps)) return false;
+  im = __builtin_amdgcn_rsqf(s2);
+  mag = s2 * im;
+  return true;
+}
+__device__ __forceinline__ bool pair_norm(double gx, double gy, double eps, double &mag, double &im) {
+  mag = sqrt(gx * gx + gy * gy);
+  if (!(mag > eps)) return false;
+  im = 1.0 / mag;
+  return true;
+}
+
 // Eq. (10) stress sum over the fluid pairs 12, 13, 23 (the double sum over ordered pairs with
 // the factor 1/2 equals the sum over unordered pairs, since G_lk = -G_kl), and the pair normals
 // n_kl = G_kl / |G_kl| (zero when |G_kl| <= eps).
@@ -224,11 +239,10 @@ __device__ __forceinline__ void pair_stress(const T cc[3], const T g[3][2], T rh
     const int k = pk[pr], l = pl[pr];
     const T Gx = cc[l] * g[k][0] - cc[k] * g[l][0];
     const T Gy = cc[l] * g[k][1] - cc[k] * g[l][1];
-    const T mag = sqrt(Gx * Gx + Gy * Gy);
     const T rk = cc[k] * rho, rl = cc[l] * rho;
     const T Akl = fmin(fmax(T(1e6) * rk * rl, T(0)), T(1));
-    if (mag > eps) {
-      const T im = rcp(mag);
+    T mag, im;
+    if (pair_norm(Gx, Gy, eps, mag, im)) {
       const T nx = Gx * im, ny = Gy * im;
       const T coef = K.sig[pr] * Akl * mag;
       txx += coef * (T(1) - nx * nx);

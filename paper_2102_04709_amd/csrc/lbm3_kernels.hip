@@ -53,13 +53,12 @@ __device__ __forceinline__ int first_item(int remap) {
 }
 
 // ------------------------------------------------------------------------------------------
-// Tile kernel: one work-group per (domain, TX x TY tile); C on tile+3 rings, stress on tile+2,
-// collision on tile+1, all in LDS.  Also provides the field export (FIELDS = true).
+// Tile kernel: one work-group per (domain, TX x TY tile); C on tile+3 rings, stress on tile+2
+// (with the recolouring vectors of tile+1), collision on tile+1, all in LDS.  Also provides the field export (FIELDS = true).
 template <typename T>
 struct Smem {
   T *C0, *C1, *C2, *RH;  // ring 3: mass fractions and total density
   T *Txx, *Txy, *Tyy;    // ring 2: stress of Eq. (10)
-  T *N;                  // ring 1, 6 planes: n12, n13, n23 (x, y)
   T *PF;                 // ring 1, 9 planes: post-collision shifted distribution
   T *PR;                 // ring 1, 4 planes: R_1, R_2 of the recolouring
   uint8_t *FL;           // ring 3: flags
@@ -69,7 +68,7 @@ template <typename T>
 __host__ __device__ inline size_t smem_bytes(int TX, int TY) {
   const size_t n3 = (size_t)(TX + 6) * (TY + 6), n2 = (size_t)(TX + 4) * (TY + 4),
                n1 = (size_t)(TX + 2) * (TY + 2);
-  return (4 * n3 + 3 * n2 + 19 * n1) * sizeof(T) + ((n3 + 15) & ~(size_t)15);
+  return (4 * n3 + 3 * n2 + 13 * n1) * sizeof(T) + ((n3 + 15) & ~(size_t)15);
 }
 
 template <typename T, int W1, int W3, int N1>
@@ -96,7 +95,6 @@ __global__ __launch_bounds__(kThreads) void step_fused(StepArgs<S, T> A) {
     T *p = reinterpret_cast<T *>(smem_raw);
     L.C0 = p; p += N3; L.C1 = p; p += N3; L.C2 = p; p += N3; L.RH = p; p += N3;
     L.Txx = p; p += N2; L.Txy = p; p += N2; L.Tyy = p; p += N2;
-    L.N = p; p += 6 * N1;
     L.PF = p; p += 9 * N1;
     L.PR = p; p += 4 * N1;
     L.FL = reinterpret_cast<uint8_t *>(p);
@@ -126,7 +124,7 @@ __global__ __launch_bounds__(kThreads) void step_fused(StepArgs<S, T> A) {
     }
     __syncthreads();
 
-    // Phase B: Eq. (12) gradients and the Eq. (10) stress on tile + 2 rings.
+    // Phase B: Eq. (12) gradients and the Eq. (10) stress on tile + 2 rings; recolouring vectors.
     for (int q = tid; q < N2; q += kThreads) {
       const int lx = q % W2, ly = q / W2;
       const int p3 = (lx + 1) + (ly + 1) * W3;
@@ -144,15 +142,20 @@ __global__ __launch_bounds__(kThreads) void step_fused(StepArgs<S, T> A) {
       T txx, txy, tyy, nrm[6];
       pair_stress(cc, g, L.RH[p3], K, eps_g, txx, txy, tyy, nrm);
       L.Txx[q] = txx; L.Txy[q] = txy; L.Tyy[q] = tyy;
-      if (lx >= 1 && lx <= W2 - 2 && ly >= 1 && ly <= H2 - 2) {
+      // Eq. (13)-(15): the recolouring vectors of the fluid nodes of tile + 1 ring, from the
+      // normals just formed (phase C needs only them, not the normals)
+      if (!FIELDS && lx >= 1 && lx <= W2 - 2 && ly >= 1 && ly <= H2 - 2 && !(L.FL[p3] & FL_SOLID)) {
         const int p1 = (lx - 1) + (ly - 1) * W1;
+        const T rt = L.RH[p3];
+        T Rv[4];
+        recolour_R(cc[0] * rt, cc[1] * rt, cc[2] * rt, rt, nrm, K, Rv);
 #pragma unroll
-        for (int c = 0; c < 6; ++c) L.N[c * N1 + p1] = nrm[c];
+        for (int c = 0; c < 4; ++c) L.PR[c * N1 + p1] = Rv[c];
       }
     }
     __syncthreads();
 
-    // Phase C: force, velocity, MRT collision and recolouring vectors on tile + 1 ring.
+    // Phase C: force, velocity and MRT collision on tile + 1 ring.
     auto phase_c = [&](int q) {
       const int lx = q % W1, ly = q / W1;
       const int p2 = (lx + 1) + (ly + 1) * W2;
@@ -192,12 +195,6 @@ __global__ __launch_bounds__(kThreads) void step_fused(StepArgs<S, T> A) {
       }
 #pragma unroll
       for (int a = 0; a < 9; ++a) L.PF[a * N1 + q] = fd[a];
-      T nrm[6], Rv[4];
-#pragma unroll
-      for (int c = 0; c < 6; ++c) nrm[c] = L.N[c * N1 + q];
-      recolour_R(r0, r1, r2, L.RH[p3], nrm, K, Rv);
-#pragma unroll
-      for (int c = 0; c < 4; ++c) L.PR[c * N1 + q] = Rv[c];
     };
     for (int q = tid; q < N1; q += kThreads) phase_c(q);
     if (FIELDS) {
