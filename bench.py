@@ -83,7 +83,7 @@ def measure(workloads_, precision, steps, warmup, graph=100, config=None):
     else:
         k, tx, ty = config
         sim = lbm3.Simulation(workloads_, precision=precision, graph_block_steps=graph, kernel=int(k),
-                              tile=(tx, ty) if k == 0 else (0, ty))
+                              tile=(tx, ty) if k in (0, 3) else (0, ty))
         tile = tuple(config)
     dt = timed_run(sim, steps, warmup)
     nodes = sim.query(1)
@@ -175,7 +175,8 @@ def main():
                          "pillar_sweep_96_f32, adjoint_512_f32|f64) and print its measurement")
     ap.add_argument("--config", default=None,
                     help="fixed kernel configuration 'KERNEL,TX,TY' for --only, as the autotuner reports "
-                         "it (0 = tiles TX x TY, 1/2 = strips of 128/256 threads with TY rows)")
+                         "it (0/3 = tiles TX x TY of 256/512 threads, 1/2 = strips of 128/256 threads "
+                         "with TY rows)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()

@@ -95,11 +95,13 @@ typedef struct {
   double beta0;              /* reference segregation parameter of Eq. (14); <= 0 selects the
                                 paper's 0.7 */
   int32_t kernel;            /* fused-step kernel: 0 = tiles (tile_x x tile_y nodes per
-                                work-group), 1 = row strips of 122 columns (128 threads),
-                                2 = row strips of 250 columns (256 threads); -1 = let
-                                lbm3_autotune choose (tiles until it runs) */
-  int32_t tile_x, tile_y;    /* tiles: the tile shape (0 = default); strips: tile_y = rows per
-                                segment (0 = default), tile_x unused */
+                                256-thread work-group), 1 = row strips of 122 columns (128
+                                threads), 2 = row strips of 250 columns (256 threads), 3 = tiles
+                                with 512-thread work-groups; -1 = let lbm3_autotune choose
+                                (tiles until it runs) */
+  int32_t tile_x, tile_y;    /* tiles: the tile shape (0 = default; 256 threads: 32x8, 16x16,
+                                64x4, 64x8; 512 threads: 16x16, 32x16, 64x8); strips: tile_y =
+                                rows per segment (0 = default), tile_x unused */
   int32_t persistent_blocks; /* > 0: the fused kernel runs this many work-groups that loop over
                                 the (domain, tile) work list; 0: one work-group per work item */
   int32_t adjoint;           /* 1: also lay out the scratch of the adjoint step (lbm3_adjoint_*);
@@ -192,7 +194,8 @@ lbm3_status lbm3_autotune(lbm3_ctx *c, int32_t steps_per_candidate, int32_t *cho
 
 /* Information: key 0 = algorithmic bytes per lattice update of the fused kernel (state read
  * once and written once), 1 = total nodes, 2 = fill nodes, 3 = interpolated-bounce-back nodes,
- * 4 = tile_x, 5 = tile_y, 6 = work items, 7 = steps taken, 8 = kernel (0 tiles, 1/2 strips). */
+ * 4 = tile_x, 5 = tile_y, 6 = work items, 7 = steps taken, 8 = kernel (0/3 tiles of 256/512
+ * threads, 1/2 strips). */
 lbm3_status lbm3_query(const lbm3_ctx *c, int32_t key, double *value);
 
 const char *lbm3_last_error(const lbm3_ctx *c);

@@ -38,8 +38,9 @@ struct Candidate {
   int kernel, tx, ty;
 };
 // Candidate configurations of the fused kernel (the autotuner picks among them).
-const Candidate kCands[] = {{MODE_TILE, 32, 8},     {MODE_TILE, 16, 16},    {MODE_TILE, 64, 4},
-                            {MODE_TILE, 64, 8},     {MODE_STRIP128, 0, 32}, {MODE_STRIP256, 0, 32},
+const Candidate kCands[] = {{MODE_TILE, 32, 8},      {MODE_TILE, 16, 16},     {MODE_TILE, 64, 4},
+                            {MODE_TILE, 64, 8},      {MODE_TILE512, 16, 16},  {MODE_TILE512, 32, 16},
+                            {MODE_TILE512, 64, 8},   {MODE_STRIP128, 0, 32},  {MODE_STRIP256, 0, 32},
                             {MODE_STRIP256, 0, 64}};
 const int kMinTileArea = 256;
 const int kMinStripRows = 8;
@@ -360,15 +361,18 @@ bool plan(const lbm3_domain *d, int n, const lbm3_options *o, std::vector<DomHos
   if (!d || n < 1) return err = "need at least one domain", false;
   if (!o) return err = "options are required", false;
   if (o->precision < 0 || o->precision > 2) return err = "bad precision", false;
-  if (o->kernel < -1 || o->kernel > 2) return err = "kernel must be -1, 0, 1 or 2", false;
+  if (o->kernel < -1 || o->kernel > 3) return err = "kernel must be -1, 0, 1, 2 or 3", false;
   if (o->tile_x < 0 || o->tile_y < 0 || o->graph_block_steps < 0 || o->persistent_blocks < 0) return err = "negative option", false;
-  if (o->kernel <= 0 && (o->tile_x > 0 || o->tile_y > 0)) {
+  const bool tiles = o->kernel <= 0 || o->kernel == MODE_TILE512;
+  if (tiles && (o->tile_x > 0 || o->tile_y > 0)) {
+    const int mode = o->kernel == MODE_TILE512 ? MODE_TILE512 : MODE_TILE;
     const int area = o->tile_x * o->tile_y;
-    if (o->tile_x <= 0 || o->tile_y <= 0 || area < kMinTileArea || !tile_supported(o->tile_x, o->tile_y) ||
-        step_smem_bytes(o->precision, MODE_TILE, o->tile_x, o->tile_y) > 160 * 1024)
-      return err = "tile shape not supported (32x8, 16x16, 64x4, 64x8 within 160 KiB of LDS)", false;
+    if (o->tile_x <= 0 || o->tile_y <= 0 || area < kMinTileArea || !tile_supported(mode, o->tile_x, o->tile_y) ||
+        step_smem_bytes(o->precision, mode, o->tile_x, o->tile_y) > 160 * 1024)
+      return err = "tile shape not supported (256 threads: 32x8, 16x16, 64x4, 64x8; 512 threads: 16x16, "
+                   "32x16, 64x8; within 160 KiB of LDS)", false;
   }
-  if (o->kernel > 0 && o->tile_y > 0 && o->tile_y < kMinStripRows) return err = "strip segments need at least 8 rows", false;
+  if (!tiles && o->tile_y > 0 && o->tile_y < kMinStripRows) return err = "strip segments need at least 8 rows", false;
   const double beta0 = o->beta0 > 0 ? o->beta0 : 0.7;
   H.assign(n, DomHost());
   for (int i = 0; i < n; ++i)
@@ -394,7 +398,7 @@ bool plan(const lbm3_domain *d, int n, const lbm3_options *o, std::vector<DomHos
     nch += (d[i].ny + 15) / 16;
     int mw = 0;
     for (const Candidate &t : kCands)
-      if (t.kernel == MODE_TILE) mw = std::max(mw, tiles_of(d[i].nx, d[i].ny, t.tx, t.ty));
+      if (is_tile_mode(t.kernel)) mw = std::max(mw, tiles_of(d[i].nx, d[i].ny, t.tx, t.ty));
     mw = std::max(mw, tiles_of(d[i].nx, d[i].ny, 122, kMinStripRows));
     if (o->tile_x > 0 && o->tile_y > 0) mw = std::max(mw, tiles_of(d[i].nx, d[i].ny, o->tile_x, o->tile_y));
     maxw += mw;
@@ -499,7 +503,7 @@ void build_work_for(lbm3_ctx *c, int mode, int tx, int ty, std::vector<WorkItem>
   for (int d = 0; d < c->n; ++d) {
     DomainDev &D = c->doms[d];
     const int off = (int)work.size();
-    if (mode == MODE_TILE) {
+    if (is_tile_mode(mode)) {
       for (int y = 0; y < D.ny; y += ty)
         for (int x = 0; x < D.nx; x += tx)
           work.push_back(WorkItem{d, x, y, std::min(x + tx, D.nx), std::min(y + ty, D.ny), 0, 0, 0});
@@ -795,7 +799,7 @@ lbm3_status lbm3_create(const lbm3_domain *d, int32_t n, const lbm3_options *o, 
   c->graph_block = o->graph_block_steps > 0 ? round_up(o->graph_block_steps, 2) : 0;
   c->persistent = o->persistent_blocks;
   c->mode = o->kernel > 0 ? o->kernel : MODE_TILE;
-  if (c->mode == MODE_TILE) {
+  if (is_tile_mode(c->mode)) {
     c->tx = o->tile_x > 0 ? o->tile_x : 32;
     c->ty = o->tile_y > 0 ? o->tile_y : 8;
   } else {
@@ -1071,8 +1075,8 @@ lbm3_status lbm3_autotune(lbm3_ctx *c, int32_t steps_per_candidate, int32_t *cho
   double best = 1e300;
   Candidate bc{c->mode, c->tx, c->ty};
   for (const Candidate &t : kCands) {
-    if (t.kernel == MODE_TILE && step_smem_bytes(c->precision, MODE_TILE, t.tx, t.ty) > 160 * 1024) continue;
-    if (t.kernel != MODE_TILE && step_smem_bytes(c->precision, t.kernel, 0, 0) > 160 * 1024) continue;
+    if (is_tile_mode(t.kernel) && step_smem_bytes(c->precision, t.kernel, t.tx, t.ty) > 160 * 1024) continue;
+    if (!is_tile_mode(t.kernel) && step_smem_bytes(c->precision, t.kernel, 0, 0) > 160 * 1024) continue;
     c->mode = t.kernel;
     c->tx = t.tx;
     c->ty = t.ty;

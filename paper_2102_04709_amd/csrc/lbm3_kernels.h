@@ -49,7 +49,8 @@ struct MassArgs {
   int *bad;
 };
 
-enum { MODE_TILE = 0, MODE_STRIP128 = 1, MODE_STRIP256 = 2 };
+enum { MODE_TILE = 0, MODE_STRIP128 = 1, MODE_STRIP256 = 2, MODE_TILE512 = 3 };
+inline bool is_tile_mode(int mode) { return mode == MODE_TILE || mode == MODE_TILE512; }
 
 template <typename T>
 hipError_t launch_fill(const FillArgs<T> &a, hipStream_t s);
@@ -58,7 +59,7 @@ hipError_t launch_step(const StepArgs<S, T> &a, int grid, int mode, bool fields,
 template <typename T>
 hipError_t launch_mass(const MassArgs<T> &a, int n_chunks, int n_dom, double *out, hipStream_t s);
 size_t step_smem_bytes(int precision, int mode, int tx, int ty);
-bool tile_supported(int tx, int ty);
+bool tile_supported(int mode, int tx, int ty);
 hipError_t init_kernel_attributes();
 
 }  // namespace lbm3

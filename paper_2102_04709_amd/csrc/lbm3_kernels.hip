@@ -84,8 +84,8 @@ struct TileAcc {
   }
 };
 
-template <typename S, typename T, bool FIELDS, int TX, int TY>
-__global__ __launch_bounds__(kThreads) void step_fused(StepArgs<S, T> A) {
+template <typename S, typename T, bool FIELDS, int TX, int TY, int NT>
+__global__ __launch_bounds__(NT) void step_fused(StepArgs<S, T> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   constexpr int W3 = TX + 6, H3 = TY + 6, N3 = W3 * H3;
   constexpr int W2 = TX + 4, H2 = TY + 4, N2 = W2 * H2;
@@ -113,7 +113,7 @@ __global__ __launch_bounds__(kThreads) void step_fused(StepArgs<S, T> A) {
     const KT<T> K = make_kt<T>(D);
 
     // Phase A: C_k and rho on tile + 3 rings (with the wetting fill at the fill nodes).
-    for (int q = tid; q < N3; q += kThreads) {
+    for (int q = tid; q < N3; q += NT) {
       const int lx = q % W3, ly = q / W3;
       const int64_t li = node_index(x0 - 3 + lx, y0 - 3 + ly, D);
       const uint8_t fl = flags[li];
@@ -125,7 +125,7 @@ __global__ __launch_bounds__(kThreads) void step_fused(StepArgs<S, T> A) {
     __syncthreads();
 
     // Phase B: Eq. (12) gradients and the Eq. (10) stress on tile + 2 rings; recolouring vectors.
-    for (int q = tid; q < N2; q += kThreads) {
+    for (int q = tid; q < N2; q += NT) {
       const int lx = q % W2, ly = q / W2;
       const int p3 = (lx + 1) + (ly + 1) * W3;
       const int off[9] = {0, 1, W3, -1, -W3, 1 + W3, -1 + W3, -1 - W3, 1 - W3};
@@ -196,10 +196,10 @@ __global__ __launch_bounds__(kThreads) void step_fused(StepArgs<S, T> A) {
 #pragma unroll
       for (int a = 0; a < 9; ++a) L.PF[a * N1 + q] = fd[a];
     };
-    for (int q = tid; q < N1; q += kThreads) phase_c(q);
+    for (int q = tid; q < N1; q += NT) phase_c(q);
     if (FIELDS) {
       // partial densities (or filled C) of the tile
-      for (int q = tid; q < TX * TY; q += kThreads) {
+      for (int q = tid; q < TX * TY; q += NT) {
         const int lx = q % TX, ly = q / TX;
         const int gx = x0 + lx, gy = y0 + ly;
         if (gx >= D.nx || gy >= D.ny) continue;
@@ -225,7 +225,7 @@ __global__ __launch_bounds__(kThreads) void step_fused(StepArgs<S, T> A) {
     // Phase D: pull-streaming into the tile, Eq. (16), with the boundary rules.
     T *Rout = A.rout + 3 * D.base;
     S *Fout = A.fout + 9 * D.base;
-    for (int q = tid; q < TX * TY; q += kThreads) {
+    for (int q = tid; q < TX * TY; q += NT) {
       const int lx = q % TX, ly = q / TX;
       const int gx = x0 + lx, gy = y0 + ly;
       if (gx >= D.nx || gy >= D.ny) continue;
@@ -461,11 +461,15 @@ hipError_t launch_fill(const FillArgs<T> &a, hipStream_t s) {
   return hipGetLastError();
 }
 
-// Tile shapes compiled into the tile kernel (LDS neighbour offsets become immediates).
-#define LBM3_TILE_SHAPES(X) X(32, 8) X(16, 16) X(64, 4) X(64, 8)
+// Tile shapes compiled into the tile kernel (LDS neighbour offsets become immediates): 256-thread
+// work-groups (MODE_TILE) and 512-thread work-groups (MODE_TILE512, fewer halo nodes per tile
+// node and half the loop trips per phase).
+#define LBM3_TILE_SHAPES(X) X(32, 8, 256) X(16, 16, 256) X(64, 4, 256) X(64, 8, 256) \
+  X(16, 16, 512) X(32, 16, 512) X(64, 8, 512)
 
-bool tile_supported(int tx, int ty) {
-#define LBM3_TS(a, b) if (tx == a && ty == b) return true;
+bool tile_supported(int mode, int tx, int ty) {
+  const int nt = mode == MODE_TILE512 ? 512 : 256;
+#define LBM3_TS(a, b, c) if (tx == a && ty == b && nt == c) return true;
   LBM3_TILE_SHAPES(LBM3_TS)
 #undef LBM3_TS
   return false;
@@ -473,12 +477,13 @@ bool tile_supported(int tx, int ty) {
 
 template <typename S, typename T>
 hipError_t launch_step(const StepArgs<S, T> &a, int grid, int mode, bool fields, hipStream_t s) {
-  if (fields || mode == MODE_TILE) {
+  if (fields || mode == MODE_TILE || mode == MODE_TILE512) {
     const size_t sm = smem_bytes<T>(a.tile_x, a.tile_y);
-#define LBM3_TL(X, Y)                                                                              \
-    if (a.tile_x == X && a.tile_y == Y) {                                                          \
-      if (fields) hipLaunchKernelGGL((step_fused<S, T, true, X, Y>), dim3(grid), dim3(kThreads), sm, s, a); \
-      else hipLaunchKernelGGL((step_fused<S, T, false, X, Y>), dim3(grid), dim3(kThreads), sm, s, a);       \
+    const int nt = (!fields && mode == MODE_TILE512) ? 512 : 256;
+#define LBM3_TL(X, Y, N)                                                                           \
+    if (a.tile_x == X && a.tile_y == Y && nt == N) {                                               \
+      if (fields) hipLaunchKernelGGL((step_fused<S, T, true, X, Y, N>), dim3(grid), dim3(N), sm, s, a); \
+      else hipLaunchKernelGGL((step_fused<S, T, false, X, Y, N>), dim3(grid), dim3(N), sm, s, a);       \
       return hipGetLastError();                                                                    \
     }
     LBM3_TILE_SHAPES(LBM3_TL)
@@ -496,14 +501,14 @@ hipError_t launch_step(const StepArgs<S, T> &a, int grid, int mode, bool fields,
 hipError_t init_kernel_attributes() {
   const int lim = 160 * 1024;
   hipError_t e = hipSuccess, r;
-#define LBM3_ATTR1(S, T, F, X, Y)                                                           \
-  r = hipFuncSetAttribute((const void *)step_fused<S, T, F, X, Y>,                            \
+#define LBM3_ATTR1(S, T, F, X, Y, N)                                                        \
+  r = hipFuncSetAttribute((const void *)step_fused<S, T, F, X, Y, N>,                         \
                           hipFuncAttributeMaxDynamicSharedMemorySize, lim);                   \
   if (r != hipSuccess) e = r;
-#define LBM3_ATTRT(X, Y)                                                                      \
-  LBM3_ATTR1(double, double, false, X, Y) LBM3_ATTR1(double, double, true, X, Y)              \
-  LBM3_ATTR1(float, float, false, X, Y) LBM3_ATTR1(float, float, true, X, Y)                  \
-  LBM3_ATTR1(__half, float, false, X, Y) LBM3_ATTR1(__half, float, true, X, Y)
+#define LBM3_ATTRT(X, Y, N)                                                                   \
+  LBM3_ATTR1(double, double, false, X, Y, N) LBM3_ATTR1(double, double, true, X, Y, N)        \
+  LBM3_ATTR1(float, float, false, X, Y, N) LBM3_ATTR1(float, float, true, X, Y, N)            \
+  LBM3_ATTR1(__half, float, false, X, Y, N) LBM3_ATTR1(__half, float, true, X, Y, N)
   LBM3_TILE_SHAPES(LBM3_ATTRT)
 #undef LBM3_ATTRT
 #undef LBM3_ATTR1
@@ -529,7 +534,8 @@ hipError_t launch_mass(const MassArgs<T> &a, int n_chunks, int n_dom, double *ou
 }
 
 size_t step_smem_bytes(int precision, int mode, int tx, int ty) {
-  if (mode == MODE_TILE) return precision == 0 ? smem_bytes<double>(tx, ty) : smem_bytes<float>(tx, ty);
+  if (mode == MODE_TILE || mode == MODE_TILE512)
+    return precision == 0 ? smem_bytes<double>(tx, ty) : smem_bytes<float>(tx, ty);
   const int nt = mode == MODE_STRIP128 ? 128 : 256;
   return precision == 0 ? strip_smem_bytes<double>(nt) : strip_smem_bytes<float>(nt);
 }

@@ -50,7 +50,7 @@ class lbm3_options(C.Structure):
     ]
 
 
-KERNELS = {"tile": 0, "strip128": 1, "strip256": 2, "auto": -1}
+KERNELS = {"tile": 0, "strip128": 1, "strip256": 2, "tile512": 3, "auto": -1}
 
 
 class Lbm3Error(RuntimeError):

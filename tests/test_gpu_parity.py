@@ -158,7 +158,8 @@ def test_execution_variants_are_bitwise_identical(precision):
     lbm3 = _lbm3()
     w = _case("random_walls_circles")
     families = {
-        "tile": [dict(), dict(tile=(32, 8)), dict(tile=(16, 16)), dict(persistent_blocks=7),
+        "tile": [dict(), dict(tile=(32, 8)), dict(tile=(16, 16)), dict(kernel="tile512", tile=(32, 16)),
+                 dict(kernel="tile512", tile=(16, 16), graph_block_steps=10), dict(persistent_blocks=7),
                  dict(graph_block_steps=8)],
         "strip": [dict(kernel="strip128", tile=(0, 16)), dict(kernel="strip256", tile=(0, 40)),
                   dict(kernel="strip128", tile=(0, 8), persistent_blocks=5),
