@@ -465,6 +465,7 @@ struct lbm3_ctx {
   std::vector<WorkItem> fwork;  // tiles of the field export
   std::vector<int> fwork_off, fwork_n;
   std::vector<WorkItem> awork;  // tiles of the adjoint over the extended grids
+  std::vector<uint8_t> hflags;  // host copy of the flag planes
   struct Params {
     double theta_deg[2], sigma[3];
   };
@@ -495,6 +496,27 @@ lbm3_status hip_fail(lbm3_ctx *c, hipError_t e, const char *what) {
     if (e_ != hipSuccess) return hip_fail(c, e_, #call);   \
   } while (0)
 
+// The kind bits of a work item (see WorkItem): whether its 3-ring halo needs no index mapping and
+// whether its tile + 1 ring streams by plain pulls.
+int32_t work_kind(const lbm3_ctx *c, const WorkItem &w) {
+  const DomainDev &D = c->doms[w.dom];
+  int32_t k = 0;
+  if (w.x0 - 3 >= 0 && w.x1 + 3 <= D.nx && w.y0 - 3 >= 0 && w.y1 + 3 <= D.ny) k |= WK_INNER;
+  bool plain = !(D.bcx != BCX_PERIODIC && (w.x0 == 0 || w.x1 == D.nx));
+  const uint8_t *fl = c->hflags.data() + D.base;
+  for (int y = w.y0 - 1; plain && y < w.y1 + 1; ++y)
+    for (int x = w.x0 - 1; plain && x < w.x1 + 1; ++x) {
+      int i = x, j = y;
+      if (D.bcx == BCX_ZOUHE) i = std::min(std::max(i, 0), D.nx - 1);
+      else i = ((i % D.nx) + D.nx) % D.nx;
+      if (D.yper) j = ((j % D.ny) + D.ny) % D.ny;
+      else j = std::min(std::max(j, -2), D.ny + 1);
+      if (fl[plane_index(i, j, D.pitch)] & FL_SOLID) plain = false;
+    }
+  if (plain) k |= WK_PLAIN;
+  return k;
+}
+
 void build_work_for(lbm3_ctx *c, int mode, int tx, int ty, std::vector<WorkItem> &work,
                     std::vector<int> *offs, std::vector<int> *counts) {
   work.clear();
@@ -518,6 +540,7 @@ void build_work_for(lbm3_ctx *c, int mode, int tx, int ty, std::vector<WorkItem>
     if (offs) (*offs)[d] = off;
     if (counts) (*counts)[d] = (int)work.size() - off;
   }
+  for (WorkItem &w : work) w.kind = work_kind(c, w);
 }
 
 // Work list of the fused step kernel (tiles or strips).  The field export always uses the tile
@@ -821,6 +844,8 @@ lbm3_status lbm3_create(const lbm3_domain *d, int32_t n, const lbm3_options *o, 
   if (e != hipSuccess) return bail(hip_fail(c, e, "hipFuncSetAttribute"));
   e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
   if (e != hipSuccess) return bail(hip_fail(c, e, "hipStreamCreateWithFlags"));
+  c->hflags.assign((size_t)L.total_plane, 0);
+  for (int i = 0; i < n; ++i) memcpy(c->hflags.data() + H[i].dd.base, H[i].flags.data(), H[i].flags.size());
   build_work(c);
   build_work_for(c, MODE_TILE, kFieldTileX, kFieldTileY, c->fwork, &c->fwork_off, &c->fwork_n);
   // chunk tables of the mass reduction
@@ -832,11 +857,10 @@ lbm3_status lbm3_create(const lbm3_domain *d, int32_t n, const lbm3_options *o, 
   chunk_first.push_back((int)chunk_dom.size());
   std::vector<FillNode> fill;
   std::vector<IbbNode> ibb;
-  std::vector<uint8_t> flags((size_t)L.total_plane);
+  const std::vector<uint8_t> &flags = c->hflags;
   for (int i = 0; i < n; ++i) {
     fill.insert(fill.end(), H[i].fill.begin(), H[i].fill.end());
     ibb.insert(ibb.end(), H[i].ibb.begin(), H[i].ibb.end());
-    memcpy(flags.data() + H[i].dd.base, H[i].flags.data(), H[i].flags.size());
   }
   std::vector<unsigned char> Fh, Rh;
   if (c->precision == LBM3_F64) init_state<double, double>(d, n, H, L.total_plane, Fh, Rh);

@@ -358,6 +358,21 @@ __device__ __forceinline__ void fluid_parts(const Acc &acc, int dx, int dy, int 
   out[2] = acc.C(2, dx, dy) * fv + w * (-(R1 + R2));
 }
 
+// Eq. (16) pull-streaming into a fluid node whose eight neighbours are fluid and whose links cross
+// no x boundary with a rule of its own: the same sums as stream_node without its branches.
+template <typename T, class Acc>
+__device__ __forceinline__ void stream_plain(const Acc &acc, T fo[9], T &ra, T &rb, T &rc) {
+  ra = rb = rc = T(0);
+#pragma unroll
+  for (int a = 0; a < 9; ++a) {
+    const int ex = lat_ex(a), ey = lat_ey(a);
+    T c[3];
+    fluid_parts<T>(acc, -ex, -ey, a, c);
+    fo[a] = acc.f(a, -ex, -ey);
+    ra += c[0]; rb += c[1]; rc += c[2];
+  }
+}
+
 // Eq. (16) pull-streaming into one fluid node (gx, gy) from the post-collision data around it,
 // with halfway / interpolated bounce-back, the fluid-1/3 exchanging periodic x boundary and the
 // Zou-He columns.  Produces the shifted total distribution and the three partial densities.

@@ -71,8 +71,12 @@ struct IbbNode {
 };
 
 // A tile (x0, y0 and the context's tile shape) or a strip (columns x0..x1-1, rows y0..y1-1).
+// kind: WK_INNER when the tile's three halo rings lie inside the grid (no index wraps or clamps),
+// WK_PLAIN when the tile and its first ring are all fluid and touch no Zou-He or fluid-
+// exchanging x boundary column (streaming is a plain pull).
+enum : int32_t { WK_INNER = 1, WK_PLAIN = 2 };
 struct WorkItem {
-  int32_t dom, x0, y0, x1, y1, pad0_, pad1_, pad2_;
+  int32_t dom, x0, y0, x1, y1, kind, pad1_, pad2_;
 };
 
 __host__ __device__ inline int64_t plane_index(int i, int j, int pitch) {

@@ -85,7 +85,7 @@ struct TileAcc {
 };
 
 template <typename S, typename T, bool FIELDS, int TX, int TY, int NT>
-__global__ __launch_bounds__(NT) void step_fused(StepArgs<S, T> A) {
+__global__ __launch_bounds__(NT, NT == 512 ? 3 : 1) void step_fused(StepArgs<S, T> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   constexpr int W3 = TX + 6, H3 = TY + 6, N3 = W3 * H3;
   constexpr int W2 = TX + 4, H2 = TY + 4, N2 = W2 * H2;
@@ -111,11 +111,13 @@ __global__ __launch_bounds__(NT) void step_fused(StepArgs<S, T> A) {
     const S *Fin = A.fin + 9 * D.base;
     const int64_t P = D.plane;
     const KT<T> K = make_kt<T>(D);
+    const bool inner = wk.kind & WK_INNER, plain = wk.kind & WK_PLAIN;
 
     // Phase A: C_k and rho on tile + 3 rings (with the wetting fill at the fill nodes).
     for (int q = tid; q < N3; q += NT) {
       const int lx = q % W3, ly = q / W3;
-      const int64_t li = node_index(x0 - 3 + lx, y0 - 3 + ly, D);
+      const int64_t li = inner ? plane_index(x0 - 3 + lx, y0 - 3 + ly, D.pitch)
+                               : node_index(x0 - 3 + lx, y0 - 3 + ly, D);
       const uint8_t fl = flags[li];
       T v[4];
       node_composition<T>(fl, Rin[li], Rin[P + li], Rin[2 * P + li], A.fillC, v);
@@ -179,7 +181,7 @@ __global__ __launch_bounds__(NT) void step_fused(StepArgs<S, T> A) {
       div_stress(xx, xy, yy, Fx, Fy);
       T f[9];
       {
-        const int64_t li = node_index(gx, gy, D);
+        const int64_t li = inner ? plane_index(gx, gy, D.pitch) : node_index(gx, gy, D);
 #pragma unroll
         for (int a = 0; a < 9; ++a) f[a] = load_s<S, T>(Fin + a * P + li);
       }
@@ -236,7 +238,8 @@ __global__ __launch_bounds__(NT) void step_fused(StepArgs<S, T> A) {
       if (fl & FL_SOLID) continue;  // solid slots keep their constant contents
       TileAcc<T, W1, W3, N1> acc{L, p1, p3};
       T fo[9], ra, rb, rc;
-      stream_node<T>(acc, gx, fl, li, D, K, A.ibb, fo, ra, rb, rc);
+      if (plain) stream_plain<T>(acc, fo, ra, rb, rc);
+      else stream_node<T>(acc, gx, fl, li, D, K, A.ibb, fo, ra, rb, rc);
 #pragma unroll
       for (int a = 0; a < 9; ++a) store_s<S, T>(Fout + a * P + li, fo[a]);
       Rout[li] = ra;
