@@ -55,11 +55,15 @@ __device__ __forceinline__ int first_item(int remap) {
 // ------------------------------------------------------------------------------------------
 // Tile kernel: one work-group per (domain, TX x TY tile); C on tile+3 rings, stress on tile+2
 // (with the recolouring vectors of tile+1), collision on tile+1, all in LDS.  Also provides the field export (FIELDS = true).
+// The stress (ring 2) is dead once the force is formed, so the post-collision populations reuse
+// its LDS; the total density is kept on ring 2, where it is read.
 template <typename T>
 struct Smem {
-  T *C0, *C1, *C2, *RH;  // ring 3: mass fractions and total density
-  T *Txx, *Txy, *Tyy;    // ring 2: stress of Eq. (10)
-  T *PF;                 // ring 1, 9 planes: post-collision shifted distribution
+  T *C0, *C1, *C2;       // ring 3: mass fractions
+  T *RH;                 // ring 2: total density
+  T *Txx, *Txy, *Tyy;    // ring 2: stress of Eq. (10) (phases B, C)
+  T *PF;                 // ring 1, 9 planes: post-collision shifted distribution (phases C, D;
+                         // same LDS as the stress)
   T *PR;                 // ring 1, 4 planes: R_1, R_2 of the recolouring
   uint8_t *FL;           // ring 3: flags
 };
@@ -68,7 +72,8 @@ template <typename T>
 __host__ __device__ inline size_t smem_bytes(int TX, int TY) {
   const size_t n3 = (size_t)(TX + 6) * (TY + 6), n2 = (size_t)(TX + 4) * (TY + 4),
                n1 = (size_t)(TX + 2) * (TY + 2);
-  return (4 * n3 + 3 * n2 + 13 * n1) * sizeof(T) + ((n3 + 15) & ~(size_t)15);
+  const size_t shared = 3 * n2 > 9 * n1 ? 3 * n2 : 9 * n1;
+  return (3 * n3 + n2 + shared + 4 * n1) * sizeof(T) + ((n3 + 15) & ~(size_t)15);
 }
 
 template <typename T, int W1, int W3, int N1>
@@ -85,7 +90,7 @@ struct TileAcc {
 };
 
 template <typename S, typename T, bool FIELDS, int TX, int TY, int NT>
-__global__ __launch_bounds__(NT, NT == 512 ? 3 : 1) void step_fused(StepArgs<S, T> A) {
+__global__ __launch_bounds__(NT, (sizeof(T) == 8 || NT == 512) ? 1 : (sizeof(S) == 2 ? 5 : 6)) void step_fused(StepArgs<S, T> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   constexpr int W3 = TX + 6, H3 = TY + 6, N3 = W3 * H3;
   constexpr int W2 = TX + 4, H2 = TY + 4, N2 = W2 * H2;
@@ -93,9 +98,9 @@ __global__ __launch_bounds__(NT, NT == 512 ? 3 : 1) void step_fused(StepArgs<S, 
   Smem<T> L;
   {
     T *p = reinterpret_cast<T *>(smem_raw);
-    L.C0 = p; p += N3; L.C1 = p; p += N3; L.C2 = p; p += N3; L.RH = p; p += N3;
-    L.Txx = p; p += N2; L.Txy = p; p += N2; L.Tyy = p; p += N2;
-    L.PF = p; p += 9 * N1;
+    L.C0 = p; p += N3; L.C1 = p; p += N3; L.C2 = p; p += N3; L.RH = p; p += N2;
+    L.Txx = p; L.Txy = p + N2; L.Tyy = p + 2 * N2;
+    L.PF = p; p += (3 * N2 > 9 * N1 ? 3 * N2 : 9 * N1);
     L.PR = p; p += 4 * N1;
     L.FL = reinterpret_cast<uint8_t *>(p);
   }
@@ -122,7 +127,8 @@ __global__ __launch_bounds__(NT, NT == 512 ? 3 : 1) void step_fused(StepArgs<S, 
       T v[4];
       node_composition<T>(fl, Rin[li], Rin[P + li], Rin[2 * P + li], A.fillC, v);
       L.FL[q] = fl;
-      L.C0[q] = v[0]; L.C1[q] = v[1]; L.C2[q] = v[2]; L.RH[q] = v[3];
+      L.C0[q] = v[0]; L.C1[q] = v[1]; L.C2[q] = v[2];
+      if (lx >= 1 && lx <= W3 - 2 && ly >= 1 && ly <= H3 - 2) L.RH[(lx - 1) + (ly - 1) * W2] = v[3];
     }
     __syncthreads();
 
@@ -142,13 +148,13 @@ __global__ __launch_bounds__(NT, NT == 512 ? 3 : 1) void step_fused(StepArgs<S, 
       }
       const T cc[3] = {L.C0[p3], L.C1[p3], L.C2[p3]};
       T txx, txy, tyy, nrm[6];
-      pair_stress(cc, g, L.RH[p3], K, eps_g, txx, txy, tyy, nrm);
+      pair_stress(cc, g, L.RH[q], K, eps_g, txx, txy, tyy, nrm);
       L.Txx[q] = txx; L.Txy[q] = txy; L.Tyy[q] = tyy;
       // Eq. (13)-(15): the recolouring vectors of the fluid nodes of tile + 1 ring, from the
       // normals just formed (phase C needs only them, not the normals)
       if (!FIELDS && lx >= 1 && lx <= W2 - 2 && ly >= 1 && ly <= H2 - 2 && !(L.FL[p3] & FL_SOLID)) {
         const int p1 = (lx - 1) + (ly - 1) * W1;
-        const T rt = L.RH[p3];
+        const T rt = L.RH[q];
         T Rv[4];
         recolour_R(cc[0] * rt, cc[1] * rt, cc[2] * rt, rt, nrm, K, Rv);
 #pragma unroll
@@ -157,18 +163,28 @@ __global__ __launch_bounds__(NT, NT == 512 ? 3 : 1) void step_fused(StepArgs<S, 
     }
     __syncthreads();
 
-    // Phase C: force, velocity and MRT collision on tile + 1 ring.
-    auto phase_c = [&](int q) {
+    // Phase C: force (all ring-1 nodes first: the populations then overwrite the stress),
+    // velocity and MRT collision on tile + 1 ring.
+    constexpr int IC = (N1 + NT - 1) / NT;
+    auto active_c = [&](int q) -> bool {
+      if (q >= N1) return false;
+      const int lx = q % W1, ly = q / W1;
+      if (L.FL[(lx + 2) + (ly + 2) * W3] & FL_SOLID) return false;
+      const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
+      if (FIELDS && !(lx >= 1 && lx <= TX && ly >= 1 && ly <= TY)) return false;
+      // Zou-He ghost columns are never streaming sources; off-grid rows are flagged solid.
+      if (D.bcx == BCX_ZOUHE && (gx < 0 || gx >= D.nx)) return false;
+      if (FIELDS && (gx >= D.nx || gy >= D.ny)) return false;
+      return true;
+    };
+    T Fxs[IC], Fys[IC];
+#pragma unroll
+    for (int it = 0; it < IC; ++it) {
+      const int q = tid + it * NT;
+      Fxs[it] = Fys[it] = T(0);
+      if (!active_c(q)) continue;
       const int lx = q % W1, ly = q / W1;
       const int p2 = (lx + 1) + (ly + 1) * W2;
-      const int p3 = (lx + 2) + (ly + 2) * W3;
-      if (L.FL[p3] & FL_SOLID) return;
-      const bool inside = lx >= 1 && lx <= TX && ly >= 1 && ly <= TY;
-      if (FIELDS && !inside) return;
-      const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
-      // Zou-He ghost columns are never streaming sources; off-grid rows are flagged solid.
-      if (D.bcx == BCX_ZOUHE && (gx < 0 || gx >= D.nx)) return;
-      if (FIELDS && (gx >= D.nx || gy >= D.ny)) return;
       const int off2[9] = {0, 1, W2, -1, -W2, 1 + W2, -1 + W2, -1 - W2, 1 - W2};
       T xx[9], xy[9], yy[9];
 #pragma unroll
@@ -177,15 +193,26 @@ __global__ __launch_bounds__(NT, NT == 512 ? 3 : 1) void step_fused(StepArgs<S, 
         xy[a] = L.Txy[p2 + off2[a]];
         yy[a] = L.Tyy[p2 + off2[a]];
       }
-      T Fx, Fy;
-      div_stress(xx, xy, yy, Fx, Fy);
+      div_stress(xx, xy, yy, Fxs[it], Fys[it]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < IC; ++it) {
+      const int q = tid + it * NT;
+      if (!active_c(q)) continue;
+      const int lx = q % W1, ly = q / W1;
+      const int p2 = (lx + 1) + (ly + 1) * W2;
+      const int p3 = (lx + 2) + (ly + 2) * W3;
+      const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
+      T Fx = Fxs[it], Fy = Fys[it];
       T f[9];
       {
         const int64_t li = inner ? plane_index(gx, gy, D.pitch) : node_index(gx, gy, D);
 #pragma unroll
         for (int a = 0; a < 9; ++a) f[a] = load_s<S, T>(Fin + a * P + li);
       }
-      const T r0 = L.C0[p3] * L.RH[p3], r1 = L.C1[p3] * L.RH[p3], r2 = L.C2[p3] * L.RH[p3];
+      const T rt = L.RH[p2];
+      const T r0 = L.C0[p3] * rt, r1 = L.C1[p3] * rt, r2 = L.C2[p3] * rt;
       T fd[9], ux, uy;
       collide_shifted(f, Fx, Fy, r0, r1, r2, K, fd, ux, uy);
       if (FIELDS) {
@@ -193,12 +220,11 @@ __global__ __launch_bounds__(NT, NT == 512 ? 3 : 1) void step_fused(StepArgs<S, 
         const int64_t n = (int64_t)D.nx * D.ny;
         if (A.out_u) { A.out_u[o] = ux; A.out_u[n + o] = uy; }
         if (A.out_force) { A.out_force[o] = Fx; A.out_force[n + o] = Fy; }
-        return;
+        continue;
       }
 #pragma unroll
       for (int a = 0; a < 9; ++a) L.PF[a * N1 + q] = fd[a];
-    };
-    for (int q = tid; q < N1; q += NT) phase_c(q);
+    }
     if (FIELDS) {
       // partial densities (or filled C) of the tile
       for (int q = tid; q < TX * TY; q += NT) {
