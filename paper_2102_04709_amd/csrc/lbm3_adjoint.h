@@ -13,18 +13,18 @@
 
 namespace lbm3 {
 
-// Planes of the adjoint scratch (each of total_aplane elements of type T).
+// Planes of the adjoint scratch (each of total_aplane elements of type T).  The forward
+// intermediates (AX_*) are written by the tile kernel in its OUT_ADJ mode.
 enum {
-  AX_C = 0,      // 4: C_k, rho of the forward state
-  AX_T = 4,      // 3: stress
-  AX_N = 7,      // 6: pair normals
-  AX_F = 13,     // 2: interfacial force
-  AX_P = 15,     // 13: post-collision shifted f (9), R (4)
-  AL_F = 28,     // 2: adjoint of F (fluid nodes)
-  AL_N = 30,     // 6: adjoint of n (fluid nodes)
-  AL_G = 36,     // 6: adjoint of the colour gradients
-  AL_C = 42,     // 4: adjoint of C_k and rho
-  A_PLANES = 46
+  AX_C = 0,      // 4: C_k, rho of the forward state (every in-grid position)
+  AX_N = 4,      // 6: pair normals (fluid nodes)
+  AX_F = 10,     // 2: interfacial force (fluid nodes)
+  AX_P = 12,     // 13: post-collision shifted f (9), R (4) (fluid nodes)
+  AL_F = 25,     // 2: adjoint of F (fluid nodes)
+  AL_N = 27,     // 6: adjoint of n (fluid nodes)
+  AL_G = 33,     // 6: adjoint of the colour gradients
+  AL_C = 39,     // 4: adjoint of C_k and rho
+  A_PLANES = 43
 };
 
 template <typename S, typename T>
@@ -48,8 +48,9 @@ struct AdjArgs {
   T eps_n;          // |G| below which the adjoint treats a pair normal as constant
 };
 
-// The adjoint of one step (every kernel, in order).  tplane = elements of one state plane summed
-// over the domains (the offset of the density planes in the state layout, over 9).
+// The transposes of one step, in order (the forward intermediates must be in the scratch).
+// tplane = elements of one state plane summed over the domains (the offset of the density
+// planes in the state layout, over 9).
 template <typename S, typename T>
 hipError_t launch_adjoint(const AdjArgs<S, T> &a, int64_t tplane, hipStream_t s);
 

@@ -29,9 +29,7 @@ template <typename T>
 __device__ __forceinline__ void aadd(T *p, T v) { unsafeAtomicAdd(p, v); }
 
 // ---- extended grid ---------------------------------------------------------------------------
-__device__ __forceinline__ int64_t aidx(const DomainDev &D, int i, int j) {
-  return D.abase + (i + 1) + (int64_t)(D.nx + 2) * (j + 2);
-}
+__device__ __forceinline__ int64_t aidx(const DomainDev &D, int i, int j) { return adj_index(D, i, j); }
 // Node whose stored data a read at (i, j) sees (the forward's node_index): periodic axes wrap,
 // the Zou-He x axis clamps to the boundary columns, a non-periodic y axis to the off-grid rows.
 __device__ __forceinline__ void cmap(const DomainDev &D, int &i, int &j) {
@@ -88,23 +86,7 @@ __device__ __forceinline__ bool tile_node(const WorkItem &wk, int &i, int &j) {
 template <typename T>
 __device__ __forceinline__ T &XP(T *X, int64_t AP, int plane, int64_t q) { return X[plane * AP + q]; }
 
-// ---- forward intermediates -----------------------------------------------------------------
-template <typename S, typename T>
-__global__ __launch_bounds__(kThreads) void adj_fwd_c(AdjArgs<S, T> A) {
-  const WorkItem wk = A.work[blockIdx.x];
-  const DomainDev &D = A.doms[wk.dom];
-  int i, j;
-  if (!tile_node(wk, i, j) || i < 0 || i >= D.nx) return;  // ghost columns hold no C
-  const int64_t li = plane_index(i, j, D.pitch);
-  const uint8_t fl = A.flags[D.base + li];
-  const T *R = A.rin + 3 * D.base;
-  T v[4];
-  node_composition<T>(fl, R[li], R[D.plane + li], R[2 * D.plane + li], A.fillC, v);
-  const int64_t q = aidx(D, i, j);
-#pragma unroll
-  for (int c = 0; c < 4; ++c) XP(A.X, A.aplane, AX_C + c, q) = v[c];
-}
-
+// ---- helpers of the transposes -----------------------------------------------------------
 template <typename T>
 __device__ __forceinline__ void c9_at(const T *X, int64_t AP, const DomainDev &D, int i, int j, int k, T c9[9]) {
 #pragma unroll
@@ -113,75 +95,6 @@ __device__ __forceinline__ void c9_at(const T *X, int64_t AP, const DomainDev &D
     cmap(D, ii, jj);
     c9[a] = X[(AX_C + k) * AP + aidx(D, ii, jj)];
   }
-}
-
-template <typename S, typename T>
-__global__ __launch_bounds__(kThreads) void adj_fwd_t(AdjArgs<S, T> A) {
-  const WorkItem wk = A.work[blockIdx.x];
-  const DomainDev &D = A.doms[wk.dom];
-  int i, j;
-  if (!tile_node(wk, i, j)) return;
-  const int64_t AP = A.aplane;
-  const KT<T> K = make_kt<T>(D);
-  T g[3][2];
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    T c9[9];
-    c9_at(A.X, AP, D, i, j, k, c9);
-    grad9(c9, g[k][0], g[k][1]);
-  }
-  int ci = i, cj = j;
-  cmap(D, ci, cj);
-  const int64_t qc = aidx(D, ci, cj);
-  const T cc[3] = {A.X[AX_C * AP + qc], A.X[(AX_C + 1) * AP + qc], A.X[(AX_C + 2) * AP + qc]};
-  T txx, txy, tyy, nrm[6];
-  pair_stress(cc, g, A.X[(AX_C + 3) * AP + qc], K, A.eps_g, txx, txy, tyy, nrm);
-  const int64_t q = aidx(D, i, j);
-  XP(A.X, AP, AX_T, q) = txx;
-  XP(A.X, AP, AX_T + 1, q) = txy;
-  XP(A.X, AP, AX_T + 2, q) = tyy;
-#pragma unroll
-  for (int c = 0; c < 6; ++c) XP(A.X, AP, AX_N + c, q) = nrm[c];
-}
-
-template <typename S, typename T>
-__global__ __launch_bounds__(kThreads) void adj_fwd_p(AdjArgs<S, T> A) {
-  const WorkItem wk = A.work[blockIdx.x];
-  const DomainDev &D = A.doms[wk.dom];
-  int i, j;
-  if (!tile_node(wk, i, j) || !fluid_node(A.flags, D, i, j)) return;
-  const int64_t AP = A.aplane;
-  const KT<T> K = make_kt<T>(D);
-  T xx[9], xy[9], yy[9];
-#pragma unroll
-  for (int a = 0; a < 9; ++a) {
-    int ii = i + lat_ex(a), jj = j + lat_ey(a);
-    tmap(D, ii, jj);
-    const int64_t q = aidx(D, ii, jj);
-    xx[a] = A.X[AX_T * AP + q];
-    xy[a] = A.X[(AX_T + 1) * AP + q];
-    yy[a] = A.X[(AX_T + 2) * AP + q];
-  }
-  T Fx, Fy;
-  div_stress(xx, xy, yy, Fx, Fy);
-  const int64_t q = aidx(D, i, j);
-  XP(A.X, AP, AX_F, q) = Fx;
-  XP(A.X, AP, AX_F + 1, q) = Fy;
-  const int64_t li = plane_index(i, j, D.pitch);
-  T f[9];
-#pragma unroll
-  for (int a = 0; a < 9; ++a) f[a] = load_s<S, T>(A.fin + 9 * D.base + a * D.plane + li);
-  const T rt = A.X[(AX_C + 3) * AP + q];
-  const T r0 = A.X[AX_C * AP + q] * rt, r1 = A.X[(AX_C + 1) * AP + q] * rt, r2 = A.X[(AX_C + 2) * AP + q] * rt;
-  T fd[9], ux, uy, nrm[6], Rv[4];
-  collide_shifted(f, Fx, Fy, r0, r1, r2, K, fd, ux, uy);
-#pragma unroll
-  for (int c = 0; c < 6; ++c) nrm[c] = A.X[(AX_N + c) * AP + q];
-  recolour_R(r0, r1, r2, rt, nrm, K, Rv);
-#pragma unroll
-  for (int a = 0; a < 9; ++a) XP(A.X, AP, AX_P + a, q) = fd[a];
-#pragma unroll
-  for (int c = 0; c < 4; ++c) XP(A.X, AP, AX_P + 9 + c, q) = Rv[c];
 }
 
 // ---- transposes ----------------------------------------------------------------------------
@@ -870,9 +783,6 @@ __global__ __launch_bounds__(kThreads) void adj_seed(const DomainDev *doms, cons
 template <typename S, typename T>
 hipError_t launch_adjoint(const AdjArgs<S, T> &a, int64_t tplane, hipStream_t s) {
   const dim3 g(a.n_work), b(kThreads);
-  hipLaunchKernelGGL((adj_fwd_c<S, T>), g, b, 0, s, a);
-  hipLaunchKernelGGL((adj_fwd_t<S, T>), g, b, 0, s, a);
-  hipLaunchKernelGGL((adj_fwd_p<S, T>), g, b, 0, s, a);
   hipLaunchKernelGGL((adj_node<S, T>), g, b, 0, s, a, tplane);
   hipLaunchKernelGGL((adj_stress<S, T>), g, b, 0, s, a);
   hipLaunchKernelGGL((adj_grad<S, T>), g, b, 0, s, a);

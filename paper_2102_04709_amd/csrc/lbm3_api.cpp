@@ -590,6 +590,8 @@ StepArgs<S, T> step_args(lbm3_ctx *c, int from) {
   a.tile_y = c->ty;
   a.eps_g = T(kEpsG);
   a.out_rho = a.out_u = a.out_force = nullptr;
+  a.adj_X = nullptr;
+  a.adj_plane = 0;
   return a;
 }
 
@@ -617,7 +619,7 @@ lbm3_status enqueue_steps_t(lbm3_ctx *c, int nsteps, hipStream_t s, hipEvent_t *
     if (ev) HIPC(c, hipEventRecord(ev[3 * k], s));
     HIPC(c, launch_fill<T>(fill_args<T>(c, c->cur), s));
     if (ev) HIPC(c, hipEventRecord(ev[3 * k + 1], s));
-    HIPC(c, (launch_step<S, T>(a, grid, c->mode, false, s)));
+    HIPC(c, (launch_step<S, T>(a, grid, c->mode, OUT_STEP, s)));
     if (ev) HIPC(c, hipEventRecord(ev[3 * k + 2], s));
     c->cur = 1 - c->cur;
   }
@@ -711,7 +713,7 @@ lbm3_status fields_t(lbm3_ctx *c, int dom, void *rho, void *u, void *force) {
   a.out_rho = reinterpret_cast<T *>(rho);
   a.out_u = reinterpret_cast<T *>(u);
   a.out_force = reinterpret_cast<T *>(force);
-  HIPC(c, (launch_step<S, T>(a, c->fwork_n[dom], MODE_TILE, true, c->stream)));
+  HIPC(c, (launch_step<S, T>(a, c->fwork_n[dom], MODE_TILE, OUT_FIELDS, c->stream)));
   return LBM3_OK;
 }
 
@@ -726,6 +728,22 @@ lbm3_status adjoint_step_t(lbm3_ctx *c, const void *state, const void *lin, void
   FillArgs<T> f = fill_args<T>(c, 0);
   f.rho = rin;
   HIPC(c, launch_fill<T>(f, c->stream));
+  {  // forward intermediates of s_t on the adjoint's tiles
+    StepArgs<S, T> sa = step_args<S, T>(c, 0);
+    sa.work = c->at<WorkItem>(c->L.off_awork);
+    sa.work_begin = 0;
+    sa.work_end = (int)c->awork.size();
+    sa.remap = 1;
+    sa.fin = fin;
+    sa.rin = rin;
+    sa.fout = nullptr;
+    sa.rout = nullptr;
+    sa.tile_x = kAdjTileX;
+    sa.tile_y = kAdjTileY;
+    sa.adj_X = c->at<T>(c->L.off_aX);
+    sa.adj_plane = c->L.aplane;
+    HIPC(c, (launch_step<S, T>(sa, round_up(sa.work_end, 8), MODE_TILE, OUT_ADJ, c->stream)));
+  }
   AdjArgs<S, T> a;
   a.doms = c->at<DomainDev>(c->L.off_doms);
   a.work = c->at<WorkItem>(c->L.off_awork);
@@ -763,7 +781,7 @@ lbm3_status time_kernels_t(lbm3_ctx *c, int n, hipEvent_t ev[3]) {
   HIPC(c, hipEventRecord(ev[0], s));
   for (int k = 0; k < n; ++k) HIPC(c, launch_fill<T>(f, s));
   HIPC(c, hipEventRecord(ev[1], s));
-  for (int k = 0; k < n; ++k) HIPC(c, (launch_step<S, T>(a, grid, c->mode, false, s)));
+  for (int k = 0; k < n; ++k) HIPC(c, (launch_step<S, T>(a, grid, c->mode, OUT_STEP, s)));
   HIPC(c, hipEventRecord(ev[2], s));
   return LBM3_OK;
 }

@@ -83,6 +83,12 @@ __host__ __device__ inline int64_t plane_index(int i, int j, int pitch) {
   return (int64_t)i + (int64_t)pitch * (j + 2);
 }
 
+// Element (i, j) of a domain's extended plane in the adjoint's scratch: columns -1..nx, rows
+// -2..ny+1.
+__host__ __device__ inline int64_t adj_index(const DomainDev &D, int i, int j) {
+  return D.abase + (i + 1) + (int64_t)(D.nx + 2) * (j + 2);
+}
+
 // ---- characteristic line (Sec. II B) ------------------------------------------------------
 // From node (pi, pj) along (dx, dy), t > 0, visit the crossings with the vertical lines
 // x = integer and the horizontal lines y = integer in increasing t.  At a horizontal line the

@@ -36,7 +36,15 @@ struct StepArgs {
   T eps_g;
   // fields mode only: [comp][ny][nx] outputs of one domain
   T *out_rho, *out_u, *out_force;
+  // adjoint-intermediates mode only: the scratch planes of the adjoint (extended grid) and their
+  // size in elements
+  T *adj_X;
+  int64_t adj_plane;
 };
+
+// What the tile kernel produces: the next state, the fields of the current state, or the
+// forward intermediates of the current state that the adjoint step reads.
+enum { OUT_STEP = 0, OUT_FIELDS = 1, OUT_ADJ = 2 };
 
 template <typename T>
 struct MassArgs {
@@ -55,7 +63,7 @@ inline bool is_tile_mode(int mode) { return mode == MODE_TILE || mode == MODE_TI
 template <typename T>
 hipError_t launch_fill(const FillArgs<T> &a, hipStream_t s);
 template <typename S, typename T>
-hipError_t launch_step(const StepArgs<S, T> &a, int grid, int mode, bool fields, hipStream_t s);
+hipError_t launch_step(const StepArgs<S, T> &a, int grid, int mode, int out, hipStream_t s);
 template <typename T>
 hipError_t launch_mass(const MassArgs<T> &a, int n_chunks, int n_dom, double *out, hipStream_t s);
 size_t step_smem_bytes(int precision, int mode, int tx, int ty);

@@ -21,6 +21,7 @@
 
 #include "lbm3_device.h"
 #include "lbm3_internal.h"
+#include "lbm3_adjoint.h"
 #include "lbm3_kernels.h"
 
 namespace lbm3 {
@@ -89,7 +90,7 @@ struct TileAcc {
   }
 };
 
-template <typename S, typename T, bool FIELDS, int TX, int TY, int NT>
+template <typename S, typename T, int OUT, int TX, int TY, int NT>
 __global__ __launch_bounds__(NT, (sizeof(T) == 8 || NT == 512) ? 1 : (sizeof(S) == 2 ? 5 : 6)) void step_fused(StepArgs<S, T> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   constexpr int W3 = TX + 6, H3 = TY + 6, N3 = W3 * H3;
@@ -104,6 +105,7 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 8 || NT == 512) ? 1 : (sizeof(S) 
     L.PR = p; p += 4 * N1;
     L.FL = reinterpret_cast<uint8_t *>(p);
   }
+  constexpr bool FIELDS = OUT == OUT_FIELDS, ADJ = OUT == OUT_ADJ;
   const int tid = threadIdx.x;
   const T eps_g = A.eps_g;
 
@@ -129,6 +131,14 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 8 || NT == 512) ? 1 : (sizeof(S) 
       L.FL[q] = fl;
       L.C0[q] = v[0]; L.C1[q] = v[1]; L.C2[q] = v[2];
       if (lx >= 1 && lx <= W3 - 2 && ly >= 1 && ly <= H3 - 2) L.RH[(lx - 1) + (ly - 1) * W2] = v[3];
+      if (ADJ) {  // C_k and rho at the tile's in-grid positions
+        const int gx = x0 - 3 + lx, gy = y0 - 3 + ly;
+        if (lx >= 3 && ly >= 3 && gx < wk.x1 && gy < wk.y1 && gx >= 0 && gx < D.nx) {
+          const int64_t a = adj_index(D, gx, gy);
+#pragma unroll
+          for (int c = 0; c < 4; ++c) A.adj_X[(AX_C + c) * A.adj_plane + a] = v[c];
+        }
+      }
     }
     __syncthreads();
 
@@ -159,6 +169,16 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 8 || NT == 512) ? 1 : (sizeof(S) 
         recolour_R(cc[0] * rt, cc[1] * rt, cc[2] * rt, rt, nrm, K, Rv);
 #pragma unroll
         for (int c = 0; c < 4; ++c) L.PR[c * N1 + p1] = Rv[c];
+        if (ADJ) {  // pair normals and recolouring vectors of the tile's fluid nodes
+          const int gx = x0 - 2 + lx, gy = y0 - 2 + ly;
+          if (lx >= 2 && ly >= 2 && gx < wk.x1 && gy < wk.y1 && gx >= 0 && gx < D.nx && gy >= 0 && gy < D.ny) {
+            const int64_t a = adj_index(D, gx, gy);
+#pragma unroll
+            for (int c = 0; c < 6; ++c) A.adj_X[(AX_N + c) * A.adj_plane + a] = nrm[c];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) A.adj_X[(AX_P + 9 + c) * A.adj_plane + a] = Rv[c];
+          }
+        }
       }
     }
     __syncthreads();
@@ -222,8 +242,22 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 8 || NT == 512) ? 1 : (sizeof(S) 
         if (A.out_force) { A.out_force[o] = Fx; A.out_force[n + o] = Fy; }
         continue;
       }
+      if (ADJ) {  // interfacial force and post-collision populations of the tile's fluid nodes
+        if (lx >= 1 && ly >= 1 && gx < wk.x1 && gy < wk.y1 && gy >= 0 && gy < D.ny) {
+          const int64_t a = adj_index(D, gx, gy);
+          A.adj_X[AX_F * A.adj_plane + a] = Fxs[it];
+          A.adj_X[(AX_F + 1) * A.adj_plane + a] = Fys[it];
+#pragma unroll
+          for (int c = 0; c < 9; ++c) A.adj_X[(AX_P + c) * A.adj_plane + a] = fd[c];
+        }
+        continue;
+      }
 #pragma unroll
       for (int a = 0; a < 9; ++a) L.PF[a * N1 + q] = fd[a];
+    }
+    if (ADJ) {
+      __syncthreads();
+      continue;
     }
     if (FIELDS) {
       // partial densities (or filled C) of the tile
@@ -505,14 +539,20 @@ bool tile_supported(int mode, int tx, int ty) {
 }
 
 template <typename S, typename T>
-hipError_t launch_step(const StepArgs<S, T> &a, int grid, int mode, bool fields, hipStream_t s) {
+hipError_t launch_step(const StepArgs<S, T> &a, int grid, int mode, int out, hipStream_t s) {
+  if (out == OUT_ADJ) {  // the adjoint's tiles: 32 x 8, 256 threads
+    if (a.tile_x != 32 || a.tile_y != 8) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((step_fused<S, T, OUT_ADJ, 32, 8, 256>), dim3(grid), dim3(256), smem_bytes<T>(32, 8), s, a);
+    return hipGetLastError();
+  }
+  const bool fields = out == OUT_FIELDS;
   if (fields || mode == MODE_TILE || mode == MODE_TILE512) {
     const size_t sm = smem_bytes<T>(a.tile_x, a.tile_y);
     const int nt = (!fields && mode == MODE_TILE512) ? 512 : 256;
 #define LBM3_TL(X, Y, N)                                                                           \
     if (a.tile_x == X && a.tile_y == Y && nt == N) {                                               \
-      if (fields) hipLaunchKernelGGL((step_fused<S, T, true, X, Y, N>), dim3(grid), dim3(N), sm, s, a); \
-      else hipLaunchKernelGGL((step_fused<S, T, false, X, Y, N>), dim3(grid), dim3(N), sm, s, a);       \
+      if (fields) hipLaunchKernelGGL((step_fused<S, T, OUT_FIELDS, X, Y, N>), dim3(grid), dim3(N), sm, s, a); \
+      else hipLaunchKernelGGL((step_fused<S, T, OUT_STEP, X, Y, N>), dim3(grid), dim3(N), sm, s, a);         \
       return hipGetLastError();                                                                    \
     }
     LBM3_TILE_SHAPES(LBM3_TL)
@@ -535,11 +575,13 @@ hipError_t init_kernel_attributes() {
                           hipFuncAttributeMaxDynamicSharedMemorySize, lim);                   \
   if (r != hipSuccess) e = r;
 #define LBM3_ATTRT(X, Y, N)                                                                   \
-  LBM3_ATTR1(double, double, false, X, Y, N) LBM3_ATTR1(double, double, true, X, Y, N)        \
-  LBM3_ATTR1(float, float, false, X, Y, N) LBM3_ATTR1(float, float, true, X, Y, N)            \
-  LBM3_ATTR1(__half, float, false, X, Y, N) LBM3_ATTR1(__half, float, true, X, Y, N)
+  LBM3_ATTR1(double, double, OUT_STEP, X, Y, N) LBM3_ATTR1(double, double, OUT_FIELDS, X, Y, N) \
+  LBM3_ATTR1(float, float, OUT_STEP, X, Y, N) LBM3_ATTR1(float, float, OUT_FIELDS, X, Y, N)     \
+  LBM3_ATTR1(__half, float, OUT_STEP, X, Y, N) LBM3_ATTR1(__half, float, OUT_FIELDS, X, Y, N)
   LBM3_TILE_SHAPES(LBM3_ATTRT)
 #undef LBM3_ATTRT
+  LBM3_ATTR1(double, double, OUT_ADJ, 32, 8, 256)
+  LBM3_ATTR1(float, float, OUT_ADJ, 32, 8, 256)
 #undef LBM3_ATTR1
 #define LBM3_ATTR2(S, T, N)                                                                   \
   r = hipFuncSetAttribute((const void *)step_strip<S, T, N>,                                  \
@@ -569,9 +611,9 @@ size_t step_smem_bytes(int precision, int mode, int tx, int ty) {
   return precision == 0 ? strip_smem_bytes<double>(nt) : strip_smem_bytes<float>(nt);
 }
 
-template hipError_t launch_step<double, double>(const StepArgs<double, double> &, int, int, bool, hipStream_t);
-template hipError_t launch_step<float, float>(const StepArgs<float, float> &, int, int, bool, hipStream_t);
-template hipError_t launch_step<__half, float>(const StepArgs<__half, float> &, int, int, bool, hipStream_t);
+template hipError_t launch_step<double, double>(const StepArgs<double, double> &, int, int, int, hipStream_t);
+template hipError_t launch_step<float, float>(const StepArgs<float, float> &, int, int, int, hipStream_t);
+template hipError_t launch_step<__half, float>(const StepArgs<__half, float> &, int, int, int, hipStream_t);
 template hipError_t launch_fill<double>(const FillArgs<double> &, hipStream_t);
 template hipError_t launch_fill<float>(const FillArgs<float> &, hipStream_t);
 template hipError_t launch_mass<double>(const MassArgs<double> &, int, int, double *, hipStream_t);
