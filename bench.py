@@ -6,7 +6,9 @@ shifted storage, advanced with hipGraph replays of 100-step blocks; MLUPS counts
 nodes.  The same JSON line carries the FP64 and FP16-storage variants, the x10 scale-up of the
 workload (4000 x 4000, 1.5 GB of FP32 state, so HBM rather than the 256 MB Infinity Cache sets
 the bound), the 96-domain batched pillar sweep in one launch per step, the roofline of the fused
-kernel from HIP events on its own stream, and the FP64 CPU oracle timed on a bounded sample.
+kernel from HIP events on its own stream, the adjoint step and the checkpointed forward +
+backward rollout on the 512 x 256 inverse problem (FP32 and FP64), and the FP64 CPU oracle
+timed on a bounded sample.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--skip-extra] [--skip-cpu]
 """
@@ -25,11 +27,21 @@ HBM_PEAK_GBS = 8000.0
 # per dispatch), scaled by what the counters read for a 1 GiB device copy in the same process
 # (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0); summaries and commands in profiles/.  Keyed by workload,
 # precision and kernel configuration, valid for the kernel sources with the given digest only.
-KERNEL_SOURCES = ("lbm3_kernels.hip", "lbm3_device.h", "lbm3_internal.h", "lbm3_kernels.h")
+KERNEL_SOURCES = ("lbm3_kernels.hip", "lbm3_device.h", "lbm3_internal.h", "lbm3_kernels.h", "lbm3_adjoint.h")
 TRAFFIC = {
-    "digest": "5a25da32dbb21d88",
-    ("cylinder_janus", 400, "f32", (0, 16, 16)): (4471.5 * 2.0 + 6969.0) * 1024,
-    ("cylinder_janus_x10", 4000, "f32", (0, 16, 16)): (431797.0 * 2.0 + 698610.1) * 1024,
+    "digest": "39a9698249397e92",
+    ("cylinder_janus", 400, "f32", (0, 16, 16)): (4492.9 * 2.0 + 6969.0 * 1.0) * 1024,
+    ("cylinder_janus", 400, "f32", (3, 16, 16)): (4467.8 * 2.0 + 6969.1 * 1.0) * 1024,
+    ("cylinder_janus", 400, "f32", (0, 32, 8)): (4365.3 * 2.0 + 6969.0 * 1.0) * 1024,
+    ("cylinder_janus", 400, "f32", (3, 32, 16)): (4479.0 * 2.0 + 6969.0 * 1.0) * 1024,
+    ("cylinder_janus", 400, "f32", (3, 64, 8)): (4350.3 * 2.0 + 6969.0 * 1.0) * 1024,
+    ("cylinder_janus", 400, "f32", (0, 64, 4)): (4291.3 * 2.0 + 6969.0 * 1.0) * 1024,
+    ("cylinder_janus", 400, "f32", (0, 64, 8)): (6254.5 * 2.0 + 11869.0 * 1.0) * 1024,
+    ("cylinder_janus", 400, "f32", (1, 0, 32)): (4646.3 * 2.0 + 7010.6 * 1.0) * 1024,
+    ("cylinder_janus", 400, "f32", (2, 0, 32)): (4128.9 * 2.0 + 6969.0 * 1.0) * 1024,
+    ("cylinder_janus", 400, "f32", (2, 0, 64)): (4128.9 * 2.0 + 6969.0 * 1.0) * 1024,
+    ("cylinder_janus_x10", 4000, "f32", (0, 32, 8)): (371376.7 * 2.0 + 696999.0 * 1.0) * 1024,
+    ("cylinder_janus_x10", 4000, "f32", (0, 16, 16)): (428507.9 * 2.0 + 699973.0 * 1.0) * 1024,
 }
 
 
