@@ -686,7 +686,7 @@ __global__ __launch_bounds__(kThreads) void adj_fill(AdjArgs<S, T> A, int64_t tp
     tk = fmin(fmax(th, LO), HI);
     const double ang = 0.5 * PI - tk, phi = fabs(ang);
     double sn, cs;
-    sincos(phi, &sn, &cs);
+    sincos_quadrant(phi, sn, cs);
     const double sg = (line & 1) ? -1.0 : 1.0;
     const double dx = cs * fn.nx - sg * sn * fn.ny, dy = cs * fn.ny + sg * sn * fn.nx;
     const LineHit h = march_line(fn.i, fn.j, dx, dy, fluid_at);

@@ -53,6 +53,18 @@ __device__ __forceinline__ void store_s(S *p, T v) {
 template <>
 __device__ __forceinline__ void store_s<__half, float>(__half *p, float v) { *p = __float2half_rn(v); }
 
+// Streaming store of the next state: written once per step and read back only by the next
+// launch, so it is marked non-temporal (the write does not displace cached neighbour rows).
+template <typename S, typename T>
+__device__ __forceinline__ void store_nt(S *p, T v) {
+  __builtin_nontemporal_store((S)v, p);
+}
+template <>
+__device__ __forceinline__ void store_nt<__half, float>(__half *p, float v) {
+  const __half h = __float2half_rn(v);
+  __builtin_nontemporal_store(*reinterpret_cast<const unsigned short *>(&h), reinterpret_cast<unsigned short *>(p));
+}
+
 __device__ __forceinline__ int wrap_small(int v, int n) {
   while (v < 0) v += n;
   while (v >= n) v -= n;
@@ -126,13 +138,13 @@ __device__ __forceinline__ void fill_lanes(const FillNode &fn, const DomainDev &
   const double tk = fmin(fmax(th, 5.0 * PI / 180.0), 175.0 * PI / 180.0);
   const double phi = fabs(0.5 * PI - tk);
   double sp, cp;
-  sincos(phi, &sp, &cp);
+  sincos_quadrant(phi, sp, cp);
   if (line & 1) sp = -sp;
   const double nx = fn.nx, ny = fn.ny, tx = -ny, ty = nx;
   double v = 0.0;
   int ok = 0;
   if (active) {
-    const LineHit h = march_line(fn.i, fn.j, cp * nx + sp * tx, cp * ny + sp * ty, fluid_at);
+    const LineHit h = march_line_masked(fn.i, fn.j, cp * nx + sp * tx, cp * ny + sp * ty, fn.mask, fluid_at);
     if (h.ok) {
       const double ca = cfrac_at(r, P, node_q(h.i0, h.j0), k), cb = cfrac_at(r, P, node_q(h.i1, h.j1), k);
       v = ca + h.w * (cb - ca);
@@ -375,12 +387,12 @@ __device__ __forceinline__ void stream_plain(const Acc &acc, T fo[9], T &ra, T &
 
 // Eq. (16) pull-streaming into one fluid node (gx, gy) from the post-collision data around it,
 // with halfway / interpolated bounce-back, the fluid-1/3 exchanging periodic x boundary and the
-// Zou-He columns.  Produces the shifted total distribution and the three partial densities.
+// Zou-He columns.  Produces the shifted total distribution and the three partial densities.  ib:
+// the node's interpolated-bounce-back record (null without curved links).
 template <typename T, class Acc>
-__device__ __forceinline__ void stream_node(const Acc &acc, int gx, uint8_t fl, int64_t li, const DomainDev &D,
-                                            const KT<T> &K, const IbbNode *ibb, T fo[9], T &ra, T &rb, T &rc) {
+__device__ __forceinline__ void stream_node(const Acc &acc, int gx, const DomainDev &D, const KT<T> &K,
+                                            const IbbNode *ib, T fo[9], T &ra, T &rb, T &rc) {
   ra = rb = rc = T(0);
-  const IbbNode *ib = ((fl & FL_CURVED) && D.n_ibb > 0) ? find_ibb(ibb, D, li) : nullptr;
 #pragma unroll
   for (int a = 0; a < 9; ++a) {
     const int ex = lat_ex(a), ey = lat_ey(a);

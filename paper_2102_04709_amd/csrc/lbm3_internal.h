@@ -75,8 +75,25 @@ struct IbbNode {
 // WK_PLAIN when the tile and its first ring are all fluid and touch no Zou-He or fluid-
 // exchanging x boundary column (streaming is a plain pull).
 enum : int32_t { WK_INNER = 1, WK_PLAIN = 2 };
+// fill_begin, fill_count: the item's range of TileFill entries when the fused step computes the
+// wetting fill of its halo itself (zero otherwise); ibb_begin, ibb_count: its range of TileIbb
+// entries (tiles of the step; zero otherwise).
 struct WorkItem {
-  int32_t dom, x0, y0, x1, y1, kind, pad1_, pad2_;
+  int32_t dom, x0, y0, x1, y1, kind, fill_begin, fill_count, ibb_begin, ibb_count, pad_[2];
+};
+
+// An interpolated-bounce-back node of a step tile: its position q = lx + TX ly in the tile and the
+// index of its IbbNode record.
+struct TileIbb {
+  int32_t q, idx;
+};
+
+// A fill node that lies in a tile's 3-ring halo region: the node's record and its position
+// q = lx + (TX + 6) ly within the tile's ring-3 block (a node can appear at several positions
+// when the block wraps a small periodic domain or is clamped at a boundary).
+struct TileFill {
+  FillNode fn;
+  int32_t q, pad_;
 };
 
 __host__ __device__ inline int64_t plane_index(int i, int j, int pitch) {
@@ -163,6 +180,96 @@ __host__ __device__ inline LineHit march_line(int pi, int pj, double dx, double 
     }
   }
   return h;
+}
+
+// march_line with the fluid tests of the node's 7 x 7 block answered by its fluid mask: the same
+// crossings in the same order with the same arithmetic, as a loop without data-dependent
+// branches, so its hit is march_line's.  A line that needs a node outside the block (or more
+// crossings than the block can hold) before it hits is marched again by march_line, which reads
+// the flags there.
+template <class FluidAt>
+__host__ __device__ inline LineHit march_line_masked(int pi, int pj, double dx, double dy, uint64_t mask,
+                                                     const FluidAt &fluid) {
+  LineHit h;
+  h.ok = 0;
+  h.i0 = h.j0 = h.i1 = h.j1 = 0;
+  h.w = 0.0;
+  const int sx = dx > kEpsDir ? 1 : (dx < -kEpsDir ? -1 : 0);
+  const int sy = dy > kEpsDir ? 1 : (dy < -kEpsDir ? -1 : 0);
+  const double ax = dx < 0 ? -dx : dx, ay = dy < 0 ? -dy : dy;
+  const double iax = sx ? 1.0 / ax : 0.0, iay = sy ? 1.0 / ay : 0.0;
+  int kx = 1, ky = 1;
+  for (int it = 0; it < 14; ++it) {
+    const double tx = sx ? (double)kx * iax : 1e300;  // t of the next vertical line
+    const double ty = sy ? (double)ky * iay : 1e300;  // t of the next horizontal line
+    const bool vert = tx <= ty;
+    if ((vert ? tx : ty) > kTMax) return h;
+    const int line = vert ? pi + sx * kx : pj + sy * ky;  // the column or row crossed
+    const double c = vert ? pj + tx * dy : pi + ty * dx;  // the other coordinate there
+    const double cr = floor(c + 0.5);
+    const bool node = fabs(c - cr) < kEpsNode;
+    const int c0 = node ? (int)cr : (int)floor(c);
+    if (vert) {
+      ++kx;
+      if (node && sy && c0 == pj + sy * ky) ++ky;
+    } else {
+      ++ky;
+      if (node && sx && c0 == pi + sx * kx) ++kx;
+    }
+    // block offsets of the crossing's node (node) or of its two interpolation nodes
+    const int a0 = vert ? line - pi : c0 - pi, b0 = vert ? c0 - pj : line - pj;
+    const int a1 = (vert || node) ? a0 : a0 + 1, b1 = (vert && !node) ? b0 + 1 : b0;
+    if (a0 < -3 || a1 > 3 || b0 < -3 || b1 > 3) break;
+    const bool f0 = (mask >> ((b0 + 3) * 7 + a0 + 3)) & 1, f1 = (mask >> ((b1 + 3) * 7 + a1 + 3)) & 1;
+    if (f0 && f1) {
+      h.ok = 1;
+      h.i0 = pi + a0; h.j0 = pj + b0; h.i1 = pi + a1; h.j1 = pj + b1;
+      h.w = node ? 0.0 : c - c0;
+      return h;
+    }
+  }
+  return march_line(pi, pj, dx, dy, fluid);
+}
+
+// sin and cos of an angle in [0, pi/2] in FP64 (the wetting fill's line angle phi), to a few
+// ulp: Taylor series of degree 19 (sine) and 20 (cosine), evaluated by Horner's rule in x^2, on
+// [0, pi/4]; above pi/4 the series run on the complementary angle pi/2 - phi (pi/2 split in two
+// doubles so that the difference is exact) and the results swap.  A short straight-line
+// sequence, unlike a general-argument sine with its range reduction.
+constexpr double taylor_coef(int n) {  // (-1)^m / n!, n = 2m or 2m + 1
+  double f = 1.0;
+  for (int k = 2; k <= n; ++k) f *= k;
+  return ((n / 2) % 2 ? -1.0 : 1.0) / f;
+}
+
+__host__ __device__ inline void sincos_quadrant(double phi, double &sn, double &cs) {
+  const double kPio2Hi = 1.5707963267948966, kPio2Lo = 6.123233995736766e-17;
+  const bool comp = phi > 0.78539816339744831;
+  const double x = comp ? (kPio2Hi - phi) + kPio2Lo : phi;
+  const double x2 = x * x;
+  double ps = taylor_coef(19);
+  ps = ps * x2 + taylor_coef(17);
+  ps = ps * x2 + taylor_coef(15);
+  ps = ps * x2 + taylor_coef(13);
+  ps = ps * x2 + taylor_coef(11);
+  ps = ps * x2 + taylor_coef(9);
+  ps = ps * x2 + taylor_coef(7);
+  ps = ps * x2 + taylor_coef(5);
+  ps = ps * x2 + taylor_coef(3);
+  const double s = x + x * x2 * ps;
+  double pc = taylor_coef(20);
+  pc = pc * x2 + taylor_coef(18);
+  pc = pc * x2 + taylor_coef(16);
+  pc = pc * x2 + taylor_coef(14);
+  pc = pc * x2 + taylor_coef(12);
+  pc = pc * x2 + taylor_coef(10);
+  pc = pc * x2 + taylor_coef(8);
+  pc = pc * x2 + taylor_coef(6);
+  pc = pc * x2 + taylor_coef(4);
+  pc = pc * x2 + taylor_coef(2);
+  const double c = 1.0 + x2 * pc;
+  sn = comp ? c : s;
+  cs = comp ? s : c;
 }
 
 }  // namespace lbm3

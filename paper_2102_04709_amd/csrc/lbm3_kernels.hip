@@ -91,7 +91,7 @@ struct TileAcc {
 };
 
 template <typename S, typename T, int OUT, int TX, int TY, int NT>
-__global__ __launch_bounds__(NT, (sizeof(T) == 8 || NT == 512) ? 1 : (sizeof(S) == 2 ? 5 : 6)) void step_fused(StepArgs<S, T> A) {
+__global__ __launch_bounds__(NT, sizeof(T) == 8 ? 1 : (NT == 512 ? 4 : (sizeof(S) == 2 ? 5 : 6))) void step_fused(StepArgs<S, T> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   constexpr int W3 = TX + 6, H3 = TY + 6, N3 = W3 * H3;
   constexpr int W2 = TX + 4, H2 = TY + 4, N2 = W2 * H2;
@@ -119,17 +119,26 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 8 || NT == 512) ? 1 : (sizeof(S) 
     const int64_t P = D.plane;
     const KT<T> K = make_kt<T>(D);
     const bool inner = wk.kind & WK_INNER, plain = wk.kind & WK_PLAIN;
+    // The in-tile fill is compiled into the 512-thread step kernels only: its FP64 line march needs
+    // more registers than the 256-thread kernels' occupancy target leaves, while the 512-thread
+    // kernels keep their two work-groups per CU with it.
+    const bool tile_fill = OUT == OUT_STEP && NT == 512 && A.tfill != nullptr;
 
-    // Phase A: C_k and rho on tile + 3 rings (with the wetting fill at the fill nodes).
+    // Phase A: C_k and rho on tile + 3 rings.  The C of the fill nodes come from the wetting
+    // fill: formed below by the tile itself (tile_fill), else read from the fill kernel's output.
     for (int q = tid; q < N3; q += NT) {
       const int lx = q % W3, ly = q / W3;
       const int64_t li = inner ? plane_index(x0 - 3 + lx, y0 - 3 + ly, D.pitch)
                                : node_index(x0 - 3 + lx, y0 - 3 + ly, D);
       const uint8_t fl = flags[li];
       T v[4];
-      node_composition<T>(fl, Rin[li], Rin[P + li], Rin[2 * P + li], A.fillC, v);
+      if (tile_fill && (fl & FL_FILL)) {
+        v[3] = T(1);
+      } else {
+        node_composition<T>(fl, Rin[li], Rin[P + li], Rin[2 * P + li], A.fillC, v);
+        L.C0[q] = v[0]; L.C1[q] = v[1]; L.C2[q] = v[2];
+      }
       L.FL[q] = fl;
-      L.C0[q] = v[0]; L.C1[q] = v[1]; L.C2[q] = v[2];
       if (lx >= 1 && lx <= W3 - 2 && ly >= 1 && ly <= H3 - 2) L.RH[(lx - 1) + (ly - 1) * W2] = v[3];
       if (ADJ) {  // C_k and rho at the tile's in-grid positions
         const int gx = x0 - 3 + lx, gy = y0 - 3 + ly;
@@ -137,6 +146,18 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 8 || NT == 512) ? 1 : (sizeof(S) 
           const int64_t a = adj_index(D, gx, gy);
 #pragma unroll
           for (int c = 0; c < 4; ++c) A.adj_X[(AX_C + c) * A.adj_plane + a] = v[c];
+        }
+      }
+    }
+    if (tile_fill) {
+      // Eq. (19)-(22) for the fill nodes of the halo block, four lanes per node, with the same
+      // arithmetic as wet_fill (so the filled C are identical)
+      for (int e = tid; e < 4 * wk.fill_count; e += NT) {
+        const TileFill &tf = A.tfill[wk.fill_begin + (e >> 2)];
+        double c1, c2;
+        fill_lanes<T>(tf.fn, D, flags, Rin, e & 3, true, c1, c2);
+        if ((e & 3) == 0) {
+          L.C0[tf.q] = (T)c1; L.C1[tf.q] = (T)c2; L.C2[tf.q] = (T)(1.0 - c1 - c2);
         }
       }
     }
@@ -284,6 +305,17 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 8 || NT == 512) ? 1 : (sizeof(S) 
     }
     __syncthreads();
 
+    // The interpolated-bounce-back records of the tile's curved nodes, mapped from their tile
+    // positions in the LDS of the total density (dead after phase C).
+    int *ibm = reinterpret_cast<int *>(L.RH);
+    if (wk.ibb_count > 0) {
+      for (int e = tid; e < wk.ibb_count; e += NT) {
+        const TileIbb t = A.tibb[wk.ibb_begin + e];
+        ibm[t.q] = t.idx;
+      }
+      __syncthreads();
+    }
+
     // Phase D: pull-streaming into the tile, Eq. (16), with the boundary rules.
     T *Rout = A.rout + 3 * D.base;
     S *Fout = A.fout + 9 * D.base;
@@ -299,12 +331,12 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 8 || NT == 512) ? 1 : (sizeof(S) 
       TileAcc<T, W1, W3, N1> acc{L, p1, p3};
       T fo[9], ra, rb, rc;
       if (plain) stream_plain<T>(acc, fo, ra, rb, rc);
-      else stream_node<T>(acc, gx, fl, li, D, K, A.ibb, fo, ra, rb, rc);
+      else stream_node<T>(acc, gx, D, K, (fl & FL_CURVED) ? A.ibb + ibm[q] : nullptr, fo, ra, rb, rc);
 #pragma unroll
-      for (int a = 0; a < 9; ++a) store_s<S, T>(Fout + a * P + li, fo[a]);
-      Rout[li] = ra;
-      Rout[P + li] = rb;
-      Rout[2 * P + li] = rc;
+      for (int a = 0; a < 9; ++a) store_nt<S, T>(Fout + a * P + li, fo[a]);
+      store_nt<T, T>(Rout + li, ra);
+      store_nt<T, T>(Rout + P + li, rb);
+      store_nt<T, T>(Rout + 2 * P + li, rc);
     }
     __syncthreads();
   }
@@ -458,12 +490,13 @@ __global__ __launch_bounds__(NT) void step_strip(StepArgs<S, T> A) {
           acc.cs[0] = mod_pos(yd - 1, 6); acc.cs[1] = s0; acc.cs[2] = mod_pos(yd + 1, 6);
           acc.ps[0] = mod_pos(yd - 1, 3); acc.ps[1] = mod_pos(yd, 3); acc.ps[2] = mod_pos(yd + 1, 3);
           T fo[9], ra, rb, rc;
-          stream_node<T>(acc, x, fl, li, D, K, A.ibb, fo, ra, rb, rc);
+          const IbbNode *ib = ((fl & FL_CURVED) && D.n_ibb > 0) ? find_ibb(A.ibb, D, li) : nullptr;
+          stream_node<T>(acc, x, D, K, ib, fo, ra, rb, rc);
 #pragma unroll
-          for (int a = 0; a < 9; ++a) store_s<S, T>(Fout + a * P + li, fo[a]);
-          Rout[li] = ra;
-          Rout[P + li] = rb;
-          Rout[2 * P + li] = rc;
+          for (int a = 0; a < 9; ++a) store_nt<S, T>(Fout + a * P + li, fo[a]);
+          store_nt<T, T>(Rout + li, ra);
+          store_nt<T, T>(Rout + P + li, rb);
+          store_nt<T, T>(Rout + 2 * P + li, rc);
         }
       }
     }

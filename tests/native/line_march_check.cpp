@@ -1,0 +1,73 @@
+// Host check of two device helpers of the wetting fill (compiled for the CPU from the product
+// header): march_line_masked must give exactly march_line's hit (same nodes, bit-identical weight)
+// for random fluid fields and directions, including lattice and rational-slope directions that
+// pass through nodes; sincos_quadrant must agree with long-double sin/cos to 1 ulp on the angle
+// range of Eq. (22)'s lines, [0, 85] degrees.
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <random>
+
+#include "lbm3_internal.h"
+
+using namespace lbm3;
+
+static double ulps(double a, double b) { return std::fabs(a - b) / (std::nextafter(std::fabs(b), 1e300) - std::fabs(b)); }
+
+int main(int argc, char **argv) {
+  const long trials = argc > 1 ? std::atol(argv[1]) : 200000;
+  std::mt19937_64 g(2102);
+  std::uniform_real_distribution<double> U(0.0, 1.0);
+  static int fl[41][41];
+  long bad = 0, hits = 0;
+  for (long trial = 0; trial < trials; ++trial) {
+    const double p = 0.2 + 0.75 * U(g);
+    const int shape = trial % 4;
+    for (int y = 0; y < 41; ++y)
+      for (int x = 0; x < 41; ++x) {
+        const int dx = x - 20, dy = y - 20;
+        const double r = U(g);
+        if (shape == 0) fl[y][x] = r < p;                                   // scattered solid
+        else if (shape == 1) fl[y][x] = dy > 0 || r < 0.1;                  // wall below
+        else if (shape == 2) fl[y][x] = dx * dx + dy * dy > 9 + 20 * U(g);  // rough disk
+        else fl[y][x] = (dx + 2 * dy) > 0 && r < 0.95;                      // inclined wall
+      }
+    fl[20][20] = 0;
+    const int pi = 7, pj = 11;  // the node, at the centre of the field
+    auto field = [&](int i, int j) -> bool {
+      const int x = i - pi + 20, y = j - pj + 20;
+      return x >= 0 && x <= 40 && y >= 0 && y <= 40 && fl[y][x];
+    };
+    uint64_t mask = 0;
+    for (int dy = -3; dy <= 3; ++dy)
+      for (int dx = -3; dx <= 3; ++dx)
+        if (field(pi + dx, pj + dy)) mask |= (uint64_t)1 << ((dy + 3) * 7 + dx + 3);
+    auto fluid = [&](int i, int j) -> bool {  // as the fill's test: the mask inside the block
+      const int dx = i - pi, dy = j - pj;
+      if (dx >= -3 && dx <= 3 && dy >= -3 && dy <= 3) return (mask >> ((dy + 3) * 7 + dx + 3)) & 1;
+      return field(i, j);
+    };
+    double ang = U(g) * 6.283185307179586;
+    if (trial % 7 == 0) ang = (int)(U(g) * 8) * 0.7853981633974483;
+    if (trial % 7 == 1) ang = std::atan2((double)((int)(U(g) * 7) - 3), (double)((int)(U(g) * 7) - 3));
+    const double dx = std::cos(ang), dy = std::sin(ang);
+    const LineHit a = march_line(pi, pj, dx, dy, fluid);
+    const LineHit b = march_line_masked(pi, pj, dx, dy, mask, fluid);
+    hits += a.ok;
+    if (a.ok != b.ok || (a.ok && (a.i0 != b.i0 || a.j0 != b.j0 || a.i1 != b.i1 || a.j1 != b.j1 || a.w != b.w))) {
+      if (++bad <= 5) std::printf("march mismatch, trial %ld angle %.17g\n", trial, ang);
+    }
+  }
+  double es = 0.0, ec = 0.0;
+  const long n = 1000000;
+  for (long k = 0; k <= n; ++k) {
+    const double phi = 1.4835298641951802 * k / n;
+    double s, c;
+    sincos_quadrant(phi, s, c);
+    es = std::fmax(es, ulps(s, (double)sinl((long double)phi)));
+    ec = std::fmax(ec, ulps(c, (double)cosl((long double)phi)));
+  }
+  std::printf("trials %ld hits %ld march mismatches %ld; sincos max ulp %.2f %.2f\n", trials, hits, bad, es, ec);
+  return (bad != 0 || es > 1.0 || ec > 1.0) ? 1 : 0;
+}
