@@ -106,11 +106,6 @@ typedef struct {
                                 the (domain, tile) work list; 0: one work-group per work item */
   int32_t adjoint;           /* 1: also lay out the scratch of the adjoint step (lbm3_adjoint_*);
                                 LBM3_F64 and LBM3_F32 only; 0: forward only */
-  int32_t separate_fill;     /* 512-thread tiles (kernel 3) only: 0 = each tile forms the
-                                Eq. (19)-(22) wetting fill of the fill nodes in its halo itself
-                                (no fill kernel per step); 1 = a separate fill kernel runs before
-                                each step (the filled values are the same either way).  The
-                                256-thread tiles and the strips always use the fill kernel. */
 } lbm3_options;
 
 /* Bytes of device workspace lbm3_create needs for n domains (d[0..n-1]) and these options. */

@@ -19,7 +19,6 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
-#include <unordered_map>
 #include <vector>
 
 #include "lbm3.h"
@@ -69,11 +68,10 @@ struct DomHost {
 
 struct Layout {
   size_t off_F[2], off_R[2], off_flags, off_fill, off_fillC, off_ibb, off_doms, off_work, off_fwork, off_partial,
-      off_chunk_dom, off_chunk_first, off_mass, off_bad, off_aX, off_awork, off_raw, off_tfill, off_tibb, total;
+      off_chunk_dom, off_chunk_first, off_mass, off_bad, off_aX, off_awork, off_raw, off_tibb, total;
   int64_t total_plane;
   int64_t aplane;  // elements of one adjoint scratch plane (all domains' extended grids)
   int n_fill, n_ibb, n_chunks, max_work, n_fwork, n_awork;
-  int64_t max_tfill;  // tile-fill entries of the candidate tile shape with the most
 };
 
 size_t s_size(int precision) { return precision == LBM3_F64 ? 8 : (precision == LBM3_F32 ? 4 : 2); }
@@ -358,75 +356,6 @@ bool validate_and_build(const lbm3_domain &d, int dom, double beta0, DomHost &H,
 
 int tiles_of(int nx, int ny, int tx, int ty) { return ((nx + tx - 1) / tx) * ((ny + ty - 1) / ty); }
 
-// Node (gx, gy) of the tile kernel's halo loads: periodic axes wrap, a Zou-He x axis clamps to
-// the boundary columns, a non-periodic y axis to the outer ghost rows.
-int64_t halo_index(int gx, int gy, const DomainDev &D) {
-  if (D.bcx == BCX_ZOUHE) gx = std::min(std::max(gx, 0), D.nx - 1);
-  else gx = ((gx % D.nx) + D.nx) % D.nx;
-  if (D.yper) gy = ((gy % D.ny) + D.ny) % D.ny;
-  else gy = std::min(std::max(gy, -2), D.ny + 1);
-  return plane_index(gx, gy, D.pitch);
-}
-
-// Tile-fill entries of one domain for tx x ty tiles: for each tile (in the order of the work
-// list), the fill nodes its ring-3 halo block loads, at the block positions the kernel loads them
-// at.  `flags` is the domain's flag plane, `fill` its n_fill records (global indices from
-// D.fill_off).  Appends to `out` and sets fill_begin / fill_count of the tiles in `items` when
-// they are given; returns the number of entries.
-int64_t tile_fill_lists(const DomainDev &D, const uint8_t *flags, const FillNode *fill, int n_fill, int tx, int ty,
-                        WorkItem *items, std::vector<TileFill> *out) {
-  if (n_fill == 0) {
-    if (items)
-      for (int y = 0, t = 0; y < D.ny; y += ty)
-        for (int x = 0; x < D.nx; x += tx, ++t) items[t].fill_begin = items[t].fill_count = 0;
-    return 0;
-  }
-  std::unordered_map<int64_t, int> at;  // plane index -> record
-  std::vector<std::vector<int>> row_x(D.ny);  // in-grid rows: sorted columns of fill nodes
-  for (int p = 0; p < n_fill; ++p) {
-    at[fill[p].li] = p;
-    if (fill[p].j >= 0 && fill[p].j < D.ny) row_x[fill[p].j].push_back(fill[p].i);
-  }
-  for (auto &r : row_x) std::sort(r.begin(), r.end());
-  const int W3 = tx + 6, H3 = ty + 6;
-  int64_t count = 0;
-  int t = 0;
-  for (int y0 = 0; y0 < D.ny; y0 += ty)
-    for (int x0 = 0; x0 < D.nx; x0 += tx, ++t) {
-      const int x1 = std::min(x0 + tx, D.nx), y1 = std::min(y0 + ty, D.ny);
-      const bool inner = x0 - 3 >= 0 && x1 + 3 <= D.nx && y0 - 3 >= 0 && y1 + 3 <= D.ny;
-      const int64_t begin = out ? (int64_t)out->size() : count;
-      bool any = !inner;
-      for (int y = y0 - 3; !any && y < y0 + ty + 3; ++y) {
-        const auto &r = row_x[y];
-        auto it = std::lower_bound(r.begin(), r.end(), x0 - 3);
-        any = it != r.end() && *it < x0 + tx + 3;
-      }
-      int64_t n_here = 0;
-      if (any)
-        for (int ly = 0; ly < H3; ++ly)
-          for (int lx = 0; lx < W3; ++lx) {
-            const int64_t li = inner ? plane_index(x0 - 3 + lx, y0 - 3 + ly, D.pitch)
-                                     : halo_index(x0 - 3 + lx, y0 - 3 + ly, D);
-            if (!(flags[li] & FL_FILL)) continue;
-            ++n_here;
-            if (out) {
-              TileFill e;
-              e.fn = fill[at.at(li)];
-              e.q = lx + ly * W3;
-              e.pad_ = 0;
-              out->push_back(e);
-            }
-          }
-      if (items) {
-        items[t].fill_begin = (int32_t)begin;
-        items[t].fill_count = (int32_t)n_here;
-      }
-      count += n_here;
-    }
-  return count;
-}
-
 bool plan(const lbm3_domain *d, int n, const lbm3_options *o, std::vector<DomHost> &H, Layout &L,
           std::string &err) {
   if (!d || n < 1) return err = "need at least one domain", false;
@@ -449,7 +378,6 @@ bool plan(const lbm3_domain *d, int n, const lbm3_options *o, std::vector<DomHos
   for (int i = 0; i < n; ++i)
     if (!validate_and_build(d[i], i, beta0, H[i], err)) return false;
   if (o->adjoint != 0 && o->adjoint != 1) return err = "adjoint must be 0 or 1", false;
-  if (o->separate_fill != 0 && o->separate_fill != 1) return err = "separate_fill must be 0 or 1", false;
   if (o->adjoint && o->precision == LBM3_F32_STORE_F16) return err = "the adjoint needs LBM3_F64 or LBM3_F32", false;
   int64_t base = 0, abase = 0, goff = 0;
   int nf = 0, ni = 0, nch = 0, maxw = 0, nfw = 0, naw = 0;
@@ -485,21 +413,6 @@ bool plan(const lbm3_domain *d, int n, const lbm3_options *o, std::vector<DomHos
   L.n_fwork = nfw;
   L.aplane = abase;
   L.n_awork = o->adjoint ? naw : 0;
-  {  // tile-fill capacity: the most entries of any tile shape the context can run with
-    std::vector<std::pair<int, int>> shapes;
-    for (const Candidate &t : kCands)
-      if (t.kernel == MODE_TILE512) shapes.push_back({t.tx, t.ty});
-    if (o->kernel == MODE_TILE512 && o->tile_x > 0 && o->tile_y > 0) shapes.push_back({o->tile_x, o->tile_y});
-    int64_t most = 0;
-    for (const auto &sh : shapes) {
-      int64_t tot = 0;
-      for (int i = 0; i < n; ++i)
-        tot += tile_fill_lists(H[i].dd, H[i].flags.data(), H[i].fill.data(), (int)H[i].fill.size(), sh.first,
-                               sh.second, nullptr, nullptr);
-      most = std::max(most, tot);
-    }
-    L.max_tfill = most;
-  }
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t r = off;
@@ -513,7 +426,6 @@ bool plan(const lbm3_domain *d, int n, const lbm3_options *o, std::vector<DomHos
   L.off_flags = take((size_t)base);
   L.off_fill = take(sizeof(FillNode) * std::max(nf, 1));
   L.off_fillC = take(3 * t_size(prec) * std::max(nf, 1));
-  L.off_tfill = take(sizeof(TileFill) * (size_t)std::max<int64_t>(L.max_tfill, 1));
   L.off_tibb = take(sizeof(TileIbb) * std::max(ni, 1));
   L.off_ibb = take(sizeof(IbbNode) * std::max(ni, 1));
   L.off_doms = take(sizeof(DomainDev) * n);
@@ -555,10 +467,8 @@ struct lbm3_ctx {
   std::vector<int> fwork_off, fwork_n;
   std::vector<WorkItem> awork;  // tiles of the adjoint over the extended grids
   std::vector<FillNode> hfill;  // host copy of the fill records (all domains)
-  std::vector<TileFill> tfill;  // tile-fill entries of the current work list
   std::vector<IbbNode> hibb;    // host copy of the interpolated-bounce-back records
   std::vector<TileIbb> tibb;    // their tile entries for the current work list (tiles only)
-  bool separate_fill = false;   // tile kernels read the fill kernel's output instead
   std::vector<uint8_t> hflags;  // host copy of the flag planes
   struct Params {
     double theta_deg[2], sigma[3];
@@ -637,16 +547,11 @@ void build_work_for(lbm3_ctx *c, int mode, int tx, int ty, std::vector<WorkItem>
   for (WorkItem &w : work) w.kind = work_kind(c, w);
 }
 
-// Whether the step's tiles form the wetting fill of their halos (no separate fill kernel): the
-// 512-thread tile kernels do unless asked not to.
-bool tile_fill_on(const lbm3_ctx *c) { return c->mode == MODE_TILE512 && !c->separate_fill; }
-
-// Work list of the fused step kernel (tiles or strips), with the tile-fill entries of tiles.  The
-// field export always uses the tile kernel with its own tile list (built once at creation).
+// Work list of the fused step kernel (tiles or strips), with the curved-node entries of tiles.
+// The field export always uses the tile kernel with its own tile list (built once at creation).
 void build_work(lbm3_ctx *c) {
   std::vector<int> offs, counts;
   build_work_for(c, c->mode, c->tx, c->ty, c->work, &offs, &counts);
-  c->tfill.clear();
   c->tibb.clear();
   if (is_tile_mode(c->mode)) {  // each curved node in the list of the tile that contains it
     std::vector<std::vector<TileIbb>> per(c->work.size());
@@ -666,12 +571,6 @@ void build_work(lbm3_ctx *c) {
       c->tibb.insert(c->tibb.end(), per[t].begin(), per[t].end());
     }
   }
-  if (!tile_fill_on(c)) return;
-  for (int d = 0; d < c->n; ++d) {
-    const DomainDev &D = c->doms[d];
-    tile_fill_lists(D, c->hflags.data() + D.base, c->hfill.data() + D.fill_off, D.n_fill, c->tx, c->ty,
-                    c->work.data() + offs[d], &c->tfill);
-  }
 }
 
 // Tiles of the adjoint kernels over each domain's extended range: columns -1..nx with a Zou-He
@@ -689,13 +588,6 @@ void build_adjoint_work(lbm3_ctx *c) {
 }
 
 lbm3_status upload_tables(lbm3_ctx *c) {
-  if ((int64_t)c->tfill.size() > c->L.max_tfill) {
-    c->err = "tile-fill entries exceed the workspace's capacity";
-    return LBM3_ENOMEM;
-  }
-  if (!c->tfill.empty())
-    HIPC(c, hipMemcpyAsync(c->at<void>(c->L.off_tfill), c->tfill.data(), sizeof(TileFill) * c->tfill.size(),
-                           hipMemcpyHostToDevice, c->stream));
   if (!c->tibb.empty())
     HIPC(c, hipMemcpyAsync(c->at<void>(c->L.off_tibb), c->tibb.data(), sizeof(TileIbb) * c->tibb.size(),
                            hipMemcpyHostToDevice, c->stream));
@@ -718,7 +610,6 @@ StepArgs<S, T> step_args(lbm3_ctx *c, int from) {
   a.flags = c->at<uint8_t>(c->L.off_flags);
   a.ibb = c->at<IbbNode>(c->L.off_ibb);
   a.fillC = c->at<T>(c->L.off_fillC);
-  a.tfill = nullptr;
   a.tibb = c->at<TileIbb>(c->L.off_tibb);
   a.remap = 0;
   a.fin = c->at<S>(c->L.off_F[from]);
@@ -752,13 +643,11 @@ lbm3_status enqueue_steps_t(lbm3_ctx *c, int nsteps, hipStream_t s, hipEvent_t *
   const int nw = (int)c->work.size();
   const bool persistent = c->persistent > 0;
   const int grid = persistent ? std::min(c->persistent, nw) : round_up(nw, 8);
-  const bool tf = tile_fill_on(c);
   for (int k = 0; k < nsteps; ++k) {
     StepArgs<S, T> a = step_args<S, T>(c, c->cur);
     a.remap = persistent ? 0 : 1;
-    if (tf) a.tfill = c->at<TileFill>(c->L.off_tfill);
     if (ev) HIPC(c, hipEventRecord(ev[3 * k], s));
-    if (!tf) HIPC(c, launch_fill<T>(fill_args<T>(c, c->cur), s));
+    HIPC(c, launch_fill<T>(fill_args<T>(c, c->cur), s));
     if (ev) HIPC(c, hipEventRecord(ev[3 * k + 1], s));
     HIPC(c, (launch_step<S, T>(a, grid, c->mode, OUT_STEP, s)));
     if (ev) HIPC(c, hipEventRecord(ev[3 * k + 2], s));
@@ -907,24 +796,20 @@ lbm3_status adjoint_step_t(lbm3_ctx *c, const void *state, const void *lin, void
   return LBM3_OK;
 }
 
-// Back-to-back launches on the current state: n wetting fills (none when the tiles form the
-// fill), then n fused steps that all compute the same next state into the other buffer (the
-// state does not advance).
+// Back-to-back launches on the current state: n wetting fills, then n fused steps that all
+// compute the same next state into the other buffer (the state does not advance).
 template <typename S, typename T>
 lbm3_status time_kernels_t(lbm3_ctx *c, int n, hipEvent_t ev[3]) {
   hipStream_t s = c->stream;
   const int nw = (int)c->work.size();
   const bool persistent = c->persistent > 0;
   const int grid = persistent ? std::min(c->persistent, nw) : round_up(nw, 8);
-  const bool tf = tile_fill_on(c);
   StepArgs<S, T> a = step_args<S, T>(c, c->cur);
   a.remap = persistent ? 0 : 1;
-  if (tf) a.tfill = c->at<TileFill>(c->L.off_tfill);
   const FillArgs<T> f = fill_args<T>(c, c->cur);
   HIPC(c, launch_fill<T>(f, s));
   HIPC(c, hipEventRecord(ev[0], s));
-  if (!tf)
-    for (int k = 0; k < n; ++k) HIPC(c, launch_fill<T>(f, s));
+  for (int k = 0; k < n; ++k) HIPC(c, launch_fill<T>(f, s));
   HIPC(c, hipEventRecord(ev[1], s));
   for (int k = 0; k < n; ++k) HIPC(c, (launch_step<S, T>(a, grid, c->mode, OUT_STEP, s)));
   HIPC(c, hipEventRecord(ev[2], s));
@@ -996,7 +881,6 @@ lbm3_status lbm3_create(const lbm3_domain *d, int32_t n, const lbm3_options *o, 
   for (int i = 0; i < n; ++i)
     c->params.push_back({{d[i].theta_deg[0], d[i].theta_deg[1]}, {d[i].sigma[0], d[i].sigma[1], d[i].sigma[2]}});
   c->adjoint = o->adjoint == 1;
-  c->separate_fill = o->separate_fill == 1;
   if (c->adjoint) build_adjoint_work(c);
   auto bail = [&](lbm3_status s) {
     g_plan_err = c->err;

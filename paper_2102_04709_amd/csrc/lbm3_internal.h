@@ -75,11 +75,9 @@ struct IbbNode {
 // WK_PLAIN when the tile and its first ring are all fluid and touch no Zou-He or fluid-
 // exchanging x boundary column (streaming is a plain pull).
 enum : int32_t { WK_INNER = 1, WK_PLAIN = 2 };
-// fill_begin, fill_count: the item's range of TileFill entries when the fused step computes the
-// wetting fill of its halo itself (zero otherwise); ibb_begin, ibb_count: its range of TileIbb
-// entries (tiles of the step; zero otherwise).
+// ibb_begin, ibb_count: the item's range of TileIbb entries (tiles of the step; zero otherwise).
 struct WorkItem {
-  int32_t dom, x0, y0, x1, y1, kind, fill_begin, fill_count, ibb_begin, ibb_count, pad_[2];
+  int32_t dom, x0, y0, x1, y1, kind, ibb_begin, ibb_count;
 };
 
 // An interpolated-bounce-back node of a step tile: its position q = lx + TX ly in the tile and the
@@ -88,13 +86,6 @@ struct TileIbb {
   int32_t q, idx;
 };
 
-// A fill node that lies in a tile's 3-ring halo region: the node's record and its position
-// q = lx + (TX + 6) ly within the tile's ring-3 block (a node can appear at several positions
-// when the block wraps a small periodic domain or is clamped at a boundary).
-struct TileFill {
-  FillNode fn;
-  int32_t q, pad_;
-};
 
 __host__ __device__ inline int64_t plane_index(int i, int j, int pitch) {
   return (int64_t)i + (int64_t)pitch * (j + 2);

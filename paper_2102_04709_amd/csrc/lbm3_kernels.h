@@ -27,9 +27,6 @@ struct StepArgs {
   const uint8_t *flags;
   const IbbNode *ibb;
   const T *fillC;  // [3 * n_fill] filled C of this step, indexed from the fill nodes' first slot
-  // tile step only: when set, each tile computes the wetting fill of the fill nodes in its halo
-  // region (entries work[w].fill_begin .. + fill_count) instead of reading fillC
-  const TileFill *tfill;
   // tile step only: the interpolated-bounce-back nodes of each tile (work[w].ibb_begin .. + ibb_count)
   const TileIbb *tibb;
   int remap;  // 1: XCD-aware mapping, one work item per work-group

@@ -119,26 +119,17 @@ __global__ __launch_bounds__(NT, sizeof(T) == 8 ? 1 : (NT == 512 ? 4 : (sizeof(S
     const int64_t P = D.plane;
     const KT<T> K = make_kt<T>(D);
     const bool inner = wk.kind & WK_INNER, plain = wk.kind & WK_PLAIN;
-    // The in-tile fill is compiled into the 512-thread step kernels only: its FP64 line march needs
-    // more registers than the 256-thread kernels' occupancy target leaves, while the 512-thread
-    // kernels keep their two work-groups per CU with it.
-    const bool tile_fill = OUT == OUT_STEP && NT == 512 && A.tfill != nullptr;
 
-    // Phase A: C_k and rho on tile + 3 rings.  The C of the fill nodes come from the wetting
-    // fill: formed below by the tile itself (tile_fill), else read from the fill kernel's output.
+    // Phase A: C_k and rho on tile + 3 rings (with the wetting fill at the fill nodes).
     for (int q = tid; q < N3; q += NT) {
       const int lx = q % W3, ly = q / W3;
       const int64_t li = inner ? plane_index(x0 - 3 + lx, y0 - 3 + ly, D.pitch)
                                : node_index(x0 - 3 + lx, y0 - 3 + ly, D);
       const uint8_t fl = flags[li];
       T v[4];
-      if (tile_fill && (fl & FL_FILL)) {
-        v[3] = T(1);
-      } else {
-        node_composition<T>(fl, Rin[li], Rin[P + li], Rin[2 * P + li], A.fillC, v);
-        L.C0[q] = v[0]; L.C1[q] = v[1]; L.C2[q] = v[2];
-      }
+      node_composition<T>(fl, Rin[li], Rin[P + li], Rin[2 * P + li], A.fillC, v);
       L.FL[q] = fl;
+      L.C0[q] = v[0]; L.C1[q] = v[1]; L.C2[q] = v[2];
       if (lx >= 1 && lx <= W3 - 2 && ly >= 1 && ly <= H3 - 2) L.RH[(lx - 1) + (ly - 1) * W2] = v[3];
       if (ADJ) {  // C_k and rho at the tile's in-grid positions
         const int gx = x0 - 3 + lx, gy = y0 - 3 + ly;
@@ -146,18 +137,6 @@ __global__ __launch_bounds__(NT, sizeof(T) == 8 ? 1 : (NT == 512 ? 4 : (sizeof(S
           const int64_t a = adj_index(D, gx, gy);
 #pragma unroll
           for (int c = 0; c < 4; ++c) A.adj_X[(AX_C + c) * A.adj_plane + a] = v[c];
-        }
-      }
-    }
-    if (tile_fill) {
-      // Eq. (19)-(22) for the fill nodes of the halo block, four lanes per node, with the same
-      // arithmetic as wet_fill (so the filled C are identical)
-      for (int e = tid; e < 4 * wk.fill_count; e += NT) {
-        const TileFill &tf = A.tfill[wk.fill_begin + (e >> 2)];
-        double c1, c2;
-        fill_lanes<T>(tf.fn, D, flags, Rin, e & 3, true, c1, c2);
-        if ((e & 3) == 0) {
-          L.C0[tf.q] = (T)c1; L.C1[tf.q] = (T)c2; L.C2[tf.q] = (T)(1.0 - c1 - c2);
         }
       }
     }

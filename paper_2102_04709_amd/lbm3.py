@@ -46,7 +46,7 @@ class lbm3_options(C.Structure):
     _fields_ = [
         ("precision", C.c_int32), ("graph_block_steps", C.c_int32), ("beta0", C.c_double),
         ("kernel", C.c_int32), ("tile_x", C.c_int32), ("tile_y", C.c_int32),
-        ("persistent_blocks", C.c_int32), ("adjoint", C.c_int32), ("separate_fill", C.c_int32),
+        ("persistent_blocks", C.c_int32), ("adjoint", C.c_int32),
     ]
 
 
@@ -128,7 +128,7 @@ class DomainArgs:
 
 
 def make_options(precision="f32", graph_block_steps=0, beta0=0.0, tile=None, persistent_blocks=0,
-                 kernel="tile", adjoint=False, separate_fill=False):
+                 kernel="tile", adjoint=False):
     o = lbm3_options()
     o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     o.graph_block_steps = int(graph_block_steps)
@@ -137,7 +137,6 @@ def make_options(precision="f32", graph_block_steps=0, beta0=0.0, tile=None, per
     o.tile_x, o.tile_y = (0, 0) if tile is None else (int(tile[0]), int(tile[1]))
     o.persistent_blocks = int(persistent_blocks)
     o.adjoint = 1 if adjoint else 0
-    o.separate_fill = 1 if separate_fill else 0
     return o
 
 
@@ -242,8 +241,7 @@ class Simulation:
     """Domains advanced together on one GPU by liblbm3."""
 
     def __init__(self, workloads, precision="f32", graph_block_steps=0, tile=None,
-                 persistent_blocks=0, beta0=0.0, device="cuda:0", kernel="tile", adjoint=False,
-                 separate_fill=False):
+                 persistent_blocks=0, beta0=0.0, device="cuda:0", kernel="tile", adjoint=False):
         import torch
 
         if not isinstance(workloads, (list, tuple)):
@@ -253,7 +251,7 @@ class Simulation:
         self.device = torch.device(device)
         self.domains = DomainArgs(self.workloads)
         self.options = make_options(precision, graph_block_steps, beta0, tile, persistent_blocks, kernel,
-                                    adjoint, separate_fill)
+                                    adjoint)
         nbytes = lbm3_workspace_bytes(self.domains, self.options)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self.stream = torch.cuda.current_stream(self.device)

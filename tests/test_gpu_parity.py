@@ -159,7 +159,7 @@ def test_execution_variants_are_bitwise_identical(precision):
     families = {
         "tile": [dict(), dict(tile=(32, 8)), dict(tile=(16, 16)), dict(kernel="tile512", tile=(32, 16)),
                  dict(kernel="tile512", tile=(16, 16), graph_block_steps=10), dict(persistent_blocks=7),
-                 dict(graph_block_steps=8), dict(separate_fill=True)],
+                 dict(graph_block_steps=8)],
         "strip": [dict(kernel="strip128", tile=(0, 16)), dict(kernel="strip256", tile=(0, 40)),
                   dict(kernel="strip128", tile=(0, 8), persistent_blocks=5),
                   dict(kernel="strip256", tile=(0, 64), graph_block_steps=10)],
@@ -184,28 +184,6 @@ def test_execution_variants_are_bitwise_identical(precision):
                 assert torch.equal(st, ref), (fam, kw)
             s.close()
     assert np.array_equal(finals["tile"], finals["strip"])
-
-
-@pytest.mark.parametrize("precision", ["f64", "f32"])
-def test_tile_fill_matches_fill_kernel(precision):
-    """Tiles that form the wetting fill of their own halo (the default) give the same states, bit
-    for bit, as the separate fill kernel, for every boundary rule and for domains smaller than a
-    tile (whose halo block wraps or clamps, so a fill node appears at several block positions)."""
-    import torch
-    lbm3 = _lbm3()
-    cases = [_case(n) for n in CASES] + [
-        W.random_mixture(20, 14, seed=3, walls=True, circles=[(10.2, 7.1, 3.0)]),
-        W.random_mixture(26, 9, seed=4, walls=True)]
-    for w in cases:
-        for kw in (dict(), dict(tile=(16, 16)), dict(tile=(64, 4)), dict(kernel="tile512", tile=(32, 16))):
-            print(f"case {w.name} {w.nx}x{w.ny} {precision} {kw}", flush=True)
-            a = lbm3.Simulation(w, precision=precision, **kw)
-            b = lbm3.Simulation(w, precision=precision, separate_fill=True, **kw)
-            a.step(25)
-            b.step(25)
-            assert torch.equal(a.get_state(), b.get_state()), (w.name, kw)
-            a.close()
-            b.close()
 
 
 def test_fp32_and_fp16_error_against_oracle():
