@@ -68,10 +68,10 @@ struct DomHost {
 
 struct Layout {
   size_t off_F[2], off_R[2], off_flags, off_fill, off_fillC, off_ibb, off_doms, off_work, off_fwork, off_partial,
-      off_chunk_dom, off_chunk_first, off_mass, off_bad, off_aX, off_awork, off_raw, off_tibb, total;
+      off_chunk_dom, off_chunk_first, off_mass, off_bad, off_aX, off_awork, off_raw, off_tibb, off_fblk, total;
   int64_t total_plane;
   int64_t aplane;  // elements of one adjoint scratch plane (all domains' extended grids)
-  int n_fill, n_ibb, n_chunks, max_work, n_fwork, n_awork;
+  int n_fill, n_ibb, n_chunks, max_work, n_fwork, n_awork, n_fblk;
 };
 
 size_t s_size(int precision) { return precision == LBM3_F64 ? 8 : (precision == LBM3_F32 ? 4 : 2); }
@@ -380,7 +380,7 @@ bool plan(const lbm3_domain *d, int n, const lbm3_options *o, std::vector<DomHos
   if (o->adjoint != 0 && o->adjoint != 1) return err = "adjoint must be 0 or 1", false;
   if (o->adjoint && o->precision == LBM3_F32_STORE_F16) return err = "the adjoint needs LBM3_F64 or LBM3_F32", false;
   int64_t base = 0, abase = 0, goff = 0;
-  int nf = 0, ni = 0, nch = 0, maxw = 0, nfw = 0, naw = 0;
+  int nf = 0, ni = 0, nch = 0, maxw = 0, nfw = 0, naw = 0, nfb = 0;
   for (int i = 0; i < n; ++i) {
     H[i].dd.base = base;
     base += H[i].dd.plane;
@@ -392,6 +392,7 @@ bool plan(const lbm3_domain *d, int n, const lbm3_options *o, std::vector<DomHos
     H[i].dd.fill_off = nf;
     H[i].dd.n_fill = (int)H[i].fill.size();
     nf += H[i].dd.n_fill;
+    nfb += (H[i].dd.n_fill + kFillNodes - 1) / kFillNodes;
     H[i].dd.ibb_off = ni;
     H[i].dd.n_ibb = (int)H[i].ibb.size();
     ni += H[i].dd.n_ibb;
@@ -407,6 +408,7 @@ bool plan(const lbm3_domain *d, int n, const lbm3_options *o, std::vector<DomHos
   const int prec = o->precision;
   L.total_plane = base;
   L.n_fill = nf;
+  L.n_fblk = nfb;
   L.n_ibb = ni;
   L.n_chunks = nch;
   L.max_work = maxw;
@@ -427,6 +429,7 @@ bool plan(const lbm3_domain *d, int n, const lbm3_options *o, std::vector<DomHos
   L.off_fill = take(sizeof(FillNode) * std::max(nf, 1));
   L.off_fillC = take(3 * t_size(prec) * std::max(nf, 1));
   L.off_tibb = take(sizeof(TileIbb) * std::max(ni, 1));
+  L.off_fblk = take(sizeof(FillBlock) * std::max(nfb, 1));
   L.off_ibb = take(sizeof(IbbNode) * std::max(ni, 1));
   L.off_doms = take(sizeof(DomainDev) * n);
   L.off_work = take(sizeof(WorkItem) * maxw);
@@ -630,6 +633,8 @@ FillArgs<T> fill_args(lbm3_ctx *c, int which) {
   FillArgs<T> f;
   f.fill = c->at<FillNode>(c->L.off_fill);
   f.n_fill = c->L.n_fill;
+  f.blocks = c->at<FillBlock>(c->L.off_fblk);
+  f.n_blocks = c->L.n_fblk;
   f.doms = c->at<DomainDev>(c->L.off_doms);
   f.flags = c->at<uint8_t>(c->L.off_flags);
   f.rho = c->at<T>(c->L.off_R[which]);
@@ -925,6 +930,12 @@ lbm3_status lbm3_create(const lbm3_domain *d, int32_t n, const lbm3_options *o, 
   CK(hipMemcpyAsync(c->at<void>(L.off_flags), flags.data(), flags.size(), hipMemcpyHostToDevice, s));
   if (!fill.empty()) CK(hipMemcpyAsync(c->at<void>(L.off_fill), fill.data(), sizeof(FillNode) * fill.size(), hipMemcpyHostToDevice, s));
   if (!ibb.empty()) CK(hipMemcpyAsync(c->at<void>(L.off_ibb), ibb.data(), sizeof(IbbNode) * ibb.size(), hipMemcpyHostToDevice, s));
+  std::vector<FillBlock> fblk;  // work-groups of the fill kernel: up to kFillNodes nodes of one domain
+  for (int i = 0; i < n; ++i)
+    for (int f0 = 0; f0 < H[i].dd.n_fill; f0 += kFillNodes)
+      fblk.push_back(FillBlock{i, H[i].dd.fill_off + f0, std::min(kFillNodes, H[i].dd.n_fill - f0), 0});
+  if (!fblk.empty())
+    CK(hipMemcpyAsync(c->at<void>(L.off_fblk), fblk.data(), sizeof(FillBlock) * fblk.size(), hipMemcpyHostToDevice, s));
   CK(hipMemcpyAsync(c->at<void>(L.off_chunk_dom), chunk_dom.data(), sizeof(int) * chunk_dom.size(), hipMemcpyHostToDevice, s));
   CK(hipMemcpyAsync(c->at<void>(L.off_chunk_first), chunk_first.data(), sizeof(int) * chunk_first.size(), hipMemcpyHostToDevice, s));
   CK(hipMemsetAsync(c->at<void>(L.off_bad), 0, sizeof(int), s));

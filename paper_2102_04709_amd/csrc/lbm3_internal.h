@@ -22,7 +22,14 @@
 
 namespace lbm3 {
 
-constexpr int kThreads = 256;  // work-group size of every kernel
+constexpr int kThreads = 256;  // work-group size of every kernel but the fill
+constexpr int kFillNodes = 32;  // fill nodes per work-group of the fill kernel (four lanes each)
+
+// A work-group of the fill kernel: fill nodes first .. first + count - 1 (count <= kFillNodes),
+// all of domain dom.
+struct FillBlock {
+  int32_t dom, first, count, pad_;
+};
 
 enum : uint8_t {
   FL_SOLID = 1,   // solid node (mask, or off-grid row of a non-periodic y boundary)

@@ -13,6 +13,8 @@ template <typename T>
 struct FillArgs {
   const FillNode *fill;
   int n_fill;
+  const FillBlock *blocks;  // the work-groups' fill ranges
+  int n_blocks;
   const DomainDev *doms;
   const uint8_t *flags;
   const T *rho;  // density planes of the current state

@@ -26,15 +26,18 @@
 
 namespace lbm3 {
 
-// Wetting-fill kernel: one thread per fill node; the three filled C's go to the compact array
-// fillC[3 * node] that the fused kernels read (so the solid slots of the state stay constant).
+// Wetting-fill kernel: four lanes per fill node, kFillNodes nodes of one domain per work-group
+// (so the domain's constants load with the node records instead of after them).  The three
+// filled C's go to the compact array fillC[3 * node] that the fused kernels read (so the solid
+// slots of the state stay constant).
 template <typename T>
-__global__ __launch_bounds__(kThreads) void wet_fill(FillArgs<T> A) {
-  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
-  const int idx = gid >> 2, line = gid & 3;
-  const bool active = idx < A.n_fill;
-  const FillNode fn = A.fill[active ? idx : 0];
-  const DomainDev &D = A.doms[fn.dom];
+__global__ __launch_bounds__(4 * kFillNodes) void wet_fill(FillArgs<T> A) {
+  const FillBlock B = A.blocks[blockIdx.x];
+  const DomainDev &D = A.doms[B.dom];
+  const int e = threadIdx.x >> 2, line = threadIdx.x & 3;
+  const bool active = e < B.count;
+  const int idx = B.first + (active ? e : 0);
+  const FillNode fn = A.fill[idx];
   double c1, c2;
   fill_lanes<T>(fn, D, A.flags + D.base, A.rho + 3 * D.base, line, active, c1, c2);
   if (active && line == 0) {
@@ -90,8 +93,11 @@ struct TileAcc {
   }
 };
 
+// Register budget (second launch bound: waves per SIMD): the FP32 kernels are held to 6 (80
+// VGPRs: six 256-thread or three 512-thread work-groups per CU, which their LDS also allows), the
+// FP16-storage ones to 5; the FP64 ones are limited by their LDS instead.
 template <typename S, typename T, int OUT, int TX, int TY, int NT>
-__global__ __launch_bounds__(NT, sizeof(T) == 8 ? 1 : (NT == 512 ? 4 : (sizeof(S) == 2 ? 5 : 6))) void step_fused(StepArgs<S, T> A) {
+__global__ __launch_bounds__(NT, sizeof(T) == 8 ? 1 : (sizeof(S) == 2 ? 5 : 6)) void step_fused(StepArgs<S, T> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   constexpr int W3 = TX + 6, H3 = TY + 6, N3 = W3 * H3;
   constexpr int W2 = TX + 4, H2 = TY + 4, N2 = W2 * H2;
@@ -531,8 +537,8 @@ __global__ void mass_final(const double *partial, const int *chunk_first, int n_
 // Launchers.
 template <typename T>
 hipError_t launch_fill(const FillArgs<T> &a, hipStream_t s) {
-  if (a.n_fill <= 0) return hipSuccess;
-  hipLaunchKernelGGL(wet_fill<T>, dim3((4 * a.n_fill + kThreads - 1) / kThreads), dim3(kThreads), 0, s, a);
+  if (a.n_fill <= 0 || a.n_blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(wet_fill<T>, dim3(a.n_blocks), dim3(4 * kFillNodes), 0, s, a);
   return hipGetLastError();
 }
 
