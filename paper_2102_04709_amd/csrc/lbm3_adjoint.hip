@@ -689,7 +689,7 @@ __global__ __launch_bounds__(kThreads) void adj_fill(AdjArgs<S, T> A, int64_t tp
     sincos_quadrant(phi, sn, cs);
     const double sg = (line & 1) ? -1.0 : 1.0;
     const double dx = cs * fn.nx - sg * sn * fn.ny, dy = cs * fn.ny + sg * sn * fn.nx;
-    const LineHit h = march_line(fn.i, fn.j, dx, dy, fluid_at);
+    const LineHit h = march_line_masked(fn.i, fn.j, dx, dy, fn.mask, fluid_at);
     if (h.ok) {
       ok = 1;
       n0 = node_q(h.i0, h.j0);
