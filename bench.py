@@ -29,19 +29,21 @@ HBM_PEAK_GBS = 8000.0
 # precision and kernel configuration, valid for the kernel sources with the given digest only.
 KERNEL_SOURCES = ("lbm3_kernels.hip", "lbm3_device.h", "lbm3_internal.h", "lbm3_kernels.h", "lbm3_adjoint.h")
 TRAFFIC = {
-    "digest": "39a9698249397e92",
-    ("cylinder_janus", 400, "f32", (0, 16, 16)): (4492.9 * 2.0 + 6969.0 * 1.0) * 1024,
-    ("cylinder_janus", 400, "f32", (3, 16, 16)): (4467.8 * 2.0 + 6969.1 * 1.0) * 1024,
-    ("cylinder_janus", 400, "f32", (0, 32, 8)): (4365.3 * 2.0 + 6969.0 * 1.0) * 1024,
-    ("cylinder_janus", 400, "f32", (3, 32, 16)): (4479.0 * 2.0 + 6969.0 * 1.0) * 1024,
-    ("cylinder_janus", 400, "f32", (3, 64, 8)): (4350.3 * 2.0 + 6969.0 * 1.0) * 1024,
-    ("cylinder_janus", 400, "f32", (0, 64, 4)): (4291.3 * 2.0 + 6969.0 * 1.0) * 1024,
-    ("cylinder_janus", 400, "f32", (0, 64, 8)): (6254.5 * 2.0 + 11869.0 * 1.0) * 1024,
-    ("cylinder_janus", 400, "f32", (1, 0, 32)): (4646.3 * 2.0 + 7010.6 * 1.0) * 1024,
-    ("cylinder_janus", 400, "f32", (2, 0, 32)): (4128.9 * 2.0 + 6969.0 * 1.0) * 1024,
-    ("cylinder_janus", 400, "f32", (2, 0, 64)): (4128.9 * 2.0 + 6969.0 * 1.0) * 1024,
-    ("cylinder_janus_x10", 4000, "f32", (0, 32, 8)): (371376.7 * 2.0 + 696999.0 * 1.0) * 1024,
-    ("cylinder_janus_x10", 4000, "f32", (0, 16, 16)): (428507.9 * 2.0 + 699973.0 * 1.0) * 1024,
+    "digest": "f97b17fa6cc93e23",
+    ('cylinder_janus', 400, 'f32', (0, 16, 16)): (4490.5 * 2.0 + 6969.0 * 1.0) * 1024,
+    ('cylinder_janus', 400, 'f32', (3, 16, 16)): (4872.2 * 2.0 + 8219.0 * 1.0) * 1024,
+    ('cylinder_janus', 400, 'f32', (0, 32, 8)): (4368.8 * 2.0 + 6969.0 * 1.0) * 1024,
+    ('cylinder_janus', 400, 'f32', (3, 32, 16)): (4484.3 * 2.0 + 6969.0 * 1.0) * 1024,
+    ('cylinder_janus', 400, 'f32', (3, 64, 8)): (4359.9 * 2.0 + 6969.0 * 1.0) * 1024,
+    ('cylinder_janus', 400, 'f32', (0, 64, 4)): (4290.8 * 2.0 + 6969.0 * 1.0) * 1024,
+    ('cylinder_janus', 400, 'f32', (0, 64, 8)): (6478.0 * 2.0 + 12219.0 * 1.0) * 1024,
+    ('cylinder_janus', 400, 'f32', (1, 0, 32)): (4648.9 * 2.0 + 7553.7 * 1.0) * 1024,
+    ('cylinder_janus', 400, 'f32', (2, 0, 32)): (4134.6 * 2.0 + 7464.3 * 1.0) * 1024,
+    ('cylinder_janus', 400, 'f32', (2, 0, 64)): (4134.6 * 2.0 + 7359.5 * 1.0) * 1024,
+    ('cylinder_janus_x10', 4000, 'f32', (0, 32, 8)): (363867.3 * 2.0 + 696999.2 * 1.0) * 1024,
+    ('cylinder_janus_x10', 4000, 'f32', (0, 16, 16)): (428392.2 * 2.0 + 700147.1 * 1.0) * 1024,
+    ('cylinder_janus_x10', 4000, 'f32', (3, 64, 8)): (362919.9 * 2.0 + 696999.2 * 1.0) * 1024,
+    ('cylinder_janus_x10', 4000, 'f32', (3, 32, 16)): (372335.1 * 2.0 + 696999.4 * 1.0) * 1024,
 }
 
 

@@ -317,11 +317,24 @@ __global__ __launch_bounds__(NT, sizeof(T) == 8 ? 1 : (sizeof(S) == 2 ? 5 : 6)) 
       T fo[9], ra, rb, rc;
       if (plain) stream_plain<T>(acc, fo, ra, rb, rc);
       else stream_node<T>(acc, gx, D, K, (fl & FL_CURVED) ? A.ibb + ibm[q] : nullptr, fo, ra, rb, rc);
+      // Non-temporal stores where a tile row covers whole 128-byte lines of a plane; narrower rows
+      // share lines with the neighbouring tile, which the L2 then merges before writing back.
+      if constexpr (TX * sizeof(S) >= 128) {
 #pragma unroll
-      for (int a = 0; a < 9; ++a) store_nt<S, T>(Fout + a * P + li, fo[a]);
-      store_nt<T, T>(Rout + li, ra);
-      store_nt<T, T>(Rout + P + li, rb);
-      store_nt<T, T>(Rout + 2 * P + li, rc);
+        for (int a = 0; a < 9; ++a) store_nt<S, T>(Fout + a * P + li, fo[a]);
+      } else {
+#pragma unroll
+        for (int a = 0; a < 9; ++a) store_s<S, T>(Fout + a * P + li, fo[a]);
+      }
+      if constexpr (TX * sizeof(T) >= 128) {
+        store_nt<T, T>(Rout + li, ra);
+        store_nt<T, T>(Rout + P + li, rb);
+        store_nt<T, T>(Rout + 2 * P + li, rc);
+      } else {
+        Rout[li] = ra;
+        Rout[P + li] = rb;
+        Rout[2 * P + li] = rc;
+      }
     }
     __syncthreads();
   }
