@@ -645,7 +645,7 @@ __global__ __launch_bounds__(kThreads) void adj_fill(AdjArgs<S, T> A, int64_t tp
   const bool work = active && lam != 0.0;  // equal in the two lanes of a fluid
   auto fluid_at = [&](int i, int j) -> bool {
     const int dx = i - fn.i, dy = j - fn.j;
-    if (dx >= -3 && dx <= 3 && dy >= -3 && dy <= 3) return (fn.mask >> ((dy + 3) * 7 + dx + 3)) & 1;
+    if (FluidMask::inside(dx, dy)) return fn.mask.fluid(dx, dy);
     if (D.bcx == BCX_ZOUHE) {
       if (i < 0 || i >= D.nx) return false;
     } else {

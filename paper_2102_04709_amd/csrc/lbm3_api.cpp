@@ -300,10 +300,10 @@ bool validate_and_build(const lbm3_domain &d, int dom, double beta0, DomHost &H,
         fn.d0a = wrapped(h0.i0, h0.j0);
         fn.d0b = wrapped(h0.i1, h0.j1);
         fn.d0w = h0.w;
-        fn.mask = 0;
-        for (int dy = -3; dy <= 3; ++dy)
-          for (int dx = -3; dx <= 3; ++dx)
-            if (fluid_at(i + dx, j + dy)) fn.mask |= (uint64_t)1 << ((dy + 3) * 7 + dx + 3);
+        fn.mask.w[0] = fn.mask.w[1] = 0;
+        for (int dy = -kMaskR; dy <= kMaskR; ++dy)
+          for (int dx = -kMaskR; dx <= kMaskR; ++dx)
+            if (fluid_at(i + dx, j + dy)) fn.mask.set(dx, dy);
         H.flags[p] |= FL_FILL;
         H.fill.push_back(fn);
       }

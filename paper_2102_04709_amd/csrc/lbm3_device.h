@@ -84,7 +84,7 @@ __device__ __forceinline__ int64_t node_index(int gx, int gy, const DomainDev &D
 // Wetting fill, Eq. (19)-(22), of one solid boundary node (the wet_fill kernel runs it for every
 // fill node once per step and writes the filled C to a compact array).  All geometry is FP64; C
 // at fluid nodes is rho_k / rho of the stored densities.  The march tests fluid nodes with the
-// node's 7 x 7 fluid mask and reads the flag plane only beyond it.
+// node's 11 x 11 fluid mask and reads the flag plane only beyond it.
 template <typename T>
 __device__ __forceinline__ double cfrac_at(const T *r, int64_t P, int64_t q, int k) {
   const double a = (double)r[q], b = (double)r[P + q], d = (double)r[2 * P + q];
@@ -102,7 +102,7 @@ __device__ __forceinline__ void fill_lanes(const FillNode &fn, const DomainDev &
   const int64_t P = D.plane;
   auto fluid_at = [&](int i, int j) -> bool {
     const int dx = i - fn.i, dy = j - fn.j;
-    if (dx >= -3 && dx <= 3 && dy >= -3 && dy <= 3) return (fn.mask >> ((dy + 3) * 7 + dx + 3)) & 1;
+    if (FluidMask::inside(dx, dy)) return fn.mask.fluid(dx, dy);
     if (D.bcx == BCX_ZOUHE) {
       if (i < 0 || i >= D.nx) return false;
     } else {

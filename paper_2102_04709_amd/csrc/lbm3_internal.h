@@ -57,6 +57,26 @@ struct DomainDev {
   double g[2];     // body acceleration
 };
 
+// Fluid indicator of the 11 x 11 block around a fill node (offsets -kMaskR..kMaskR): bit
+// (dy + kMaskR) * kMaskW + (dx + kMaskR) of the two words.  Most characteristic lines hit within
+// it, so their march reads no memory.
+constexpr int kMaskR = 5, kMaskW = 2 * kMaskR + 1;
+
+struct FluidMask {
+  uint64_t w[2];
+  __host__ __device__ static bool inside(int dx, int dy) {
+    return dx >= -kMaskR && dx <= kMaskR && dy >= -kMaskR && dy <= kMaskR;
+  }
+  __host__ __device__ bool fluid(int dx, int dy) const {  // for offsets inside the block
+    const int b = (dy + kMaskR) * kMaskW + dx + kMaskR;
+    return ((b < 64 ? w[0] >> b : w[1] >> (b - 64)) & 1) != 0;
+  }
+  void set(int dx, int dy) {
+    const int b = (dy + kMaskR) * kMaskW + dx + kMaskR;
+    w[b >> 6] |= (uint64_t)1 << (b & 63);
+  }
+};
+
 // A solid node whose C is filled (C_SB or C_SB2), with its fluid-pointing unit normal and the
 // point D0 where its normal line first meets the fluid (two plane indices and a weight; the
 // normal is fixed, so D0 is found once at set-up).
@@ -65,8 +85,7 @@ struct FillNode {
   int32_t d0a, d0b;       // plane indices of the interpolation nodes of D0
   double d0w;             // C(D0) = C(d0a) + d0w (C(d0b) - C(d0a))
   double nx, ny;
-  uint64_t mask;          // fluid indicator of the 7 x 7 block around the node:
-                          // bit (dy+3)*7 + (dx+3) for offsets -3..3
+  FluidMask mask;         // fluid indicator of the block around the node
 };
 
 // A fluid node with interpolated-bounce-back links: q[a-1] for direction a = 1..8 is the
@@ -180,13 +199,13 @@ __host__ __device__ inline LineHit march_line(int pi, int pj, double dx, double 
   return h;
 }
 
-// march_line with the fluid tests of the node's 7 x 7 block answered by its fluid mask: the same
+// march_line with the fluid tests of the node's 11 x 11 block answered by its fluid mask: the same
 // crossings in the same order with the same arithmetic, as a loop without data-dependent
 // branches, so its hit is march_line's.  A line that needs a node outside the block (or more
 // crossings than the block can hold) before it hits is marched again by march_line, which reads
 // the flags there.
 template <class FluidAt>
-__host__ __device__ inline LineHit march_line_masked(int pi, int pj, double dx, double dy, uint64_t mask,
+__host__ __device__ inline LineHit march_line_masked(int pi, int pj, double dx, double dy, const FluidMask &mask,
                                                      const FluidAt &fluid) {
   LineHit h;
   h.ok = 0;
@@ -197,7 +216,7 @@ __host__ __device__ inline LineHit march_line_masked(int pi, int pj, double dx, 
   const double ax = dx < 0 ? -dx : dx, ay = dy < 0 ? -dy : dy;
   const double iax = sx ? 1.0 / ax : 0.0, iay = sy ? 1.0 / ay : 0.0;
   int kx = 1, ky = 1;
-  for (int it = 0; it < 14; ++it) {
+  for (int it = 0; it < 4 * kMaskR + 2; ++it) {
     const double tx = sx ? (double)kx * iax : 1e300;  // t of the next vertical line
     const double ty = sy ? (double)ky * iay : 1e300;  // t of the next horizontal line
     const bool vert = tx <= ty;
@@ -217,8 +236,8 @@ __host__ __device__ inline LineHit march_line_masked(int pi, int pj, double dx, 
     // block offsets of the crossing's node (node) or of its two interpolation nodes
     const int a0 = vert ? line - pi : c0 - pi, b0 = vert ? c0 - pj : line - pj;
     const int a1 = (vert || node) ? a0 : a0 + 1, b1 = (vert && !node) ? b0 + 1 : b0;
-    if (a0 < -3 || a1 > 3 || b0 < -3 || b1 > 3) break;
-    const bool f0 = (mask >> ((b0 + 3) * 7 + a0 + 3)) & 1, f1 = (mask >> ((b1 + 3) * 7 + a1 + 3)) & 1;
+    if (a0 < -kMaskR || a1 > kMaskR || b0 < -kMaskR || b1 > kMaskR) break;
+    const bool f0 = mask.fluid(a0, b0), f1 = mask.fluid(a1, b1);
     if (f0 && f1) {
       h.ok = 1;
       h.i0 = pi + a0; h.j0 = pj + b0; h.i1 = pi + a1; h.j1 = pj + b1;

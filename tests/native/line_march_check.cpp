@@ -1,5 +1,5 @@
 // Host check of two device helpers of the wetting fill (compiled for the CPU from the product
-// header): march_line_masked must give exactly march_line's hit (same nodes, bit-identical weight)
+// header): march_line_masked (11 x 11 mask block) must give exactly march_line's hit (same nodes, bit-identical weight)
 // for random fluid fields and directions, including lattice and rational-slope directions that
 // pass through nodes; sincos_quadrant must agree with long-double sin/cos to 1 ulp on the angle
 // range of Eq. (22)'s lines, [0, 85] degrees.
@@ -39,13 +39,14 @@ int main(int argc, char **argv) {
       const int x = i - pi + 20, y = j - pj + 20;
       return x >= 0 && x <= 40 && y >= 0 && y <= 40 && fl[y][x];
     };
-    uint64_t mask = 0;
-    for (int dy = -3; dy <= 3; ++dy)
-      for (int dx = -3; dx <= 3; ++dx)
-        if (field(pi + dx, pj + dy)) mask |= (uint64_t)1 << ((dy + 3) * 7 + dx + 3);
+    FluidMask mask;
+    mask.w[0] = mask.w[1] = 0;
+    for (int dy = -kMaskR; dy <= kMaskR; ++dy)
+      for (int dx = -kMaskR; dx <= kMaskR; ++dx)
+        if (field(pi + dx, pj + dy)) mask.set(dx, dy);
     auto fluid = [&](int i, int j) -> bool {  // as the fill's test: the mask inside the block
       const int dx = i - pi, dy = j - pj;
-      if (dx >= -3 && dx <= 3 && dy >= -3 && dy <= 3) return (mask >> ((dy + 3) * 7 + dx + 3)) & 1;
+      if (FluidMask::inside(dx, dy)) return mask.fluid(dx, dy);
       return field(i, j);
     };
     double ang = U(g) * 6.283185307179586;
