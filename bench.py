@@ -145,6 +145,9 @@ def measure_adjoint(w, precision, steps=40, rollout_steps=400, every=100):
                         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                         "kernel": "adjoint step (all kernels of lbm3_adjoint_step)", "bytes_per_lup": bpl,
                         "lups_per_launch": nodes}}
+    if rollout_steps <= 0:
+        sim.close()
+        return res
     # checkpointed rollout: forward with checkpoints, backward with recompute and adjoint steps
     s0 = sim.get_state()
     params = rollout.params_of([w]).requires_grad_(True)
@@ -186,7 +189,7 @@ def main():
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--only", default=None,
                     help="run one workload (cylinder_400_f32|f64|f16, cylinder_4000_f32|f64|f16, "
-                         "pillar_sweep_96_f32, adjoint_512_f32|f64) and print its measurement")
+                         "pillar_sweep_96_f32, adjoint_512_f32|f64, adjoint_4000_f32) and print its measurement")
     ap.add_argument("--config", default=None,
                     help="fixed kernel configuration 'KERNEL,TX,TY' for --only, as the autotuner reports "
                          "it (0/3 = tiles TX x TY of 256/512 threads, 1/2 = strips of 128/256 threads "
@@ -214,6 +217,10 @@ def main():
         name = args.only
         if name.startswith("adjoint_512"):
             r = measure_adjoint(W.inverse_problem(), name.rsplit("_", 1)[1])
+            print(json.dumps({"workload": name, **r}), flush=True)
+            return
+        if name.startswith("adjoint_4000"):
+            r = measure_adjoint(W.cylinder_janus_hbm(10), name.rsplit("_", 1)[1], steps=6, rollout_steps=0)
             print(json.dumps({"workload": name, **r}), flush=True)
             return
         if name.startswith("pillar_sweep"):
@@ -258,6 +265,8 @@ def main():
         for p in ("f32", "f64"):
             log(f"variant: adjoint step, inverse problem 512x256 {p}")
             extra[f"adjoint_512_{p}"] = measure_adjoint(W.inverse_problem(), p)
+        log("adjoint step at HBM scale: 4000x4000 cylinder, f32")
+        extra["adjoint_4000_f32"] = measure_adjoint(W.cylinder_janus_hbm(10), "f32", steps=6, rollout_steps=0)
         out["variants"] = extra
         out["roofline_hbm"] = extra["cylinder_4000_f32"]["roofline"]
     if not args.skip_cpu:
