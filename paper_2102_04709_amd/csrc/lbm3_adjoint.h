@@ -19,12 +19,13 @@ enum {
   AX_C = 0,      // 4: C_k, rho of the forward state (every in-grid position)
   AX_N = 4,      // 6: pair normals (fluid nodes)
   AX_F = 10,     // 2: interfacial force (fluid nodes)
-  AX_P = 12,     // 13: post-collision shifted f (9), R (4) (fluid nodes)
-  AL_F = 25,     // 2: adjoint of F (fluid nodes)
-  AL_N = 27,     // 6: adjoint of n (fluid nodes)
-  AL_G = 33,     // 6: adjoint of the colour gradients
-  AL_C = 39,     // 4: adjoint of C_k and rho
-  A_PLANES = 43
+  AX_P = 12,     // 9: post-collision shifted f (fluid nodes of the two columns next to a Zou-He
+                 //    outlet, whose node reads its neighbours'; elsewhere recomputed where needed)
+  AL_F = 21,     // 2: adjoint of F (fluid nodes)
+  AL_N = 23,     // 6: adjoint of n (fluid nodes)
+  AL_G = 29,     // 6: adjoint of the colour gradients
+  AL_C = 35,     // 4: adjoint of C_k and rho
+  A_PLANES = 39
 };
 
 template <typename S, typename T>

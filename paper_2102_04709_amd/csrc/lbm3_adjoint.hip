@@ -146,7 +146,7 @@ __device__ __forceinline__ T zh_add(const DomainDev &D, bool inlet, int d, const
 // collision transpose to them at once (adj_node).
 template <typename S, typename T>
 __device__ __forceinline__ void stream_gather(const AdjArgs<S, T> &A, const DomainDev &D, int i, int j, int64_t tplane,
-                                              T lP[13], T lC[3]) {
+                                              const T fp[9], T lP[13], T lC[3]) {
   const int64_t AP = A.aplane;
   const int64_t P = D.plane;
   const int64_t li = plane_index(i, j, D.pitch);
@@ -155,9 +155,6 @@ __device__ __forceinline__ void stream_gather(const AdjArgs<S, T> &A, const Doma
   const T *Lr = A.lin + 9 * tplane + 3 * D.base;
   const bool zh = D.bcx == BCX_ZOUHE;
   const T C[3] = {A.X[AX_C * AP + q], A.X[(AX_C + 1) * AP + q], A.X[(AX_C + 2) * AP + q]};
-  T fp[9];
-#pragma unroll
-  for (int a = 0; a < 9; ++a) fp[a] = A.X[(AX_P + a) * AP + q];
 #pragma unroll
   for (int c = 0; c < 13; ++c) lP[c] = T(0);
 #pragma unroll
@@ -412,8 +409,6 @@ __global__ __launch_bounds__(kThreads) void adj_node(AdjArgs<S, T> A, int64_t tp
 #pragma unroll
       for (int c = 0; c < 4; ++c) A.X[(AL_C + c) * AP + q] = T(0);
     } else {
-      T lP[13], lCs[3];
-      stream_gather(A, D, i, j, tplane, lP, lCs);
       const int64_t li = plane_index(i, j, D.pitch);
       const KT<T> K = make_kt<T>(D);
       T f[9], C[3], nrm[6];
@@ -422,6 +417,13 @@ __global__ __launch_bounds__(kThreads) void adj_node(AdjArgs<S, T> A, int64_t tp
 #pragma unroll
       for (int c = 0; c < 3; ++c) C[c] = A.X[(AX_C + c) * AP + q];
       const T rt = A.X[(AX_C + 3) * AP + q];
+      T fd[9];  // the node's post-collision populations, recomputed as the forward step formed them
+      {
+        T Fx = A.X[AX_F * AP + q], Fy = A.X[(AX_F + 1) * AP + q], ux, uy;
+        collide_shifted(f, Fx, Fy, C[0] * rt, C[1] * rt, C[2] * rt, K, fd, ux, uy);
+      }
+      T lP[13], lCs[3];
+      stream_gather(A, D, i, j, tplane, fd, lP, lCs);
 #pragma unroll
       for (int c = 0; c < 6; ++c) nrm[c] = A.X[(AX_N + c) * AP + q];
       T lf[9], lFx, lFy, lC[3], lrt, ln[6], lgX[3];

@@ -175,14 +175,12 @@ __global__ __launch_bounds__(NT, sizeof(T) == 8 ? 1 : (sizeof(S) == 2 ? 5 : 6)) 
         recolour_R(cc[0] * rt, cc[1] * rt, cc[2] * rt, rt, nrm, K, Rv);
 #pragma unroll
         for (int c = 0; c < 4; ++c) L.PR[c * N1 + p1] = Rv[c];
-        if (ADJ) {  // pair normals and recolouring vectors of the tile's fluid nodes
+        if (ADJ) {  // pair normals of the tile's fluid nodes
           const int gx = x0 - 2 + lx, gy = y0 - 2 + ly;
           if (lx >= 2 && ly >= 2 && gx < wk.x1 && gy < wk.y1 && gx >= 0 && gx < D.nx && gy >= 0 && gy < D.ny) {
             const int64_t a = adj_index(D, gx, gy);
 #pragma unroll
             for (int c = 0; c < 6; ++c) A.adj_X[(AX_N + c) * A.adj_plane + a] = nrm[c];
-#pragma unroll
-            for (int c = 0; c < 4; ++c) A.adj_X[(AX_P + 9 + c) * A.adj_plane + a] = Rv[c];
           }
         }
       }
@@ -248,13 +246,17 @@ __global__ __launch_bounds__(NT, sizeof(T) == 8 ? 1 : (sizeof(S) == 2 ? 5 : 6)) 
         if (A.out_force) { A.out_force[o] = Fx; A.out_force[n + o] = Fy; }
         continue;
       }
-      if (ADJ) {  // interfacial force and post-collision populations of the tile's fluid nodes
+      if (ADJ) {  // interfacial force of the tile's fluid nodes; the post-collision populations
+                  // only in the two columns a Zou-He outlet node reads them from (the adjoint's
+                  // node kernel recomputes its own)
         if (lx >= 1 && ly >= 1 && gx < wk.x1 && gy < wk.y1 && gy >= 0 && gy < D.ny) {
           const int64_t a = adj_index(D, gx, gy);
           A.adj_X[AX_F * A.adj_plane + a] = Fxs[it];
           A.adj_X[(AX_F + 1) * A.adj_plane + a] = Fys[it];
+          if (D.bcx == BCX_ZOUHE && gx >= D.nx - 2) {
 #pragma unroll
-          for (int c = 0; c < 9; ++c) A.adj_X[(AX_P + c) * A.adj_plane + a] = fd[c];
+            for (int c = 0; c < 9; ++c) A.adj_X[(AX_P + c) * A.adj_plane + a] = fd[c];
+          }
         }
         continue;
       }
