@@ -77,6 +77,15 @@ __device__ __forceinline__ void block_add(const double (&v)[N], double *dst) {
 }
 
 // Node (i, j) of the 32 x 8 tile handled by this thread.
+// Work item of this work-group: consecutive items go to the same XCD (gfx950 dispatches
+// work-group b to XCD b mod 8), so the tiles an XCD processes are contiguous and share their halo
+// rows in that XCD's L2.  The grid is a multiple of 8; the padding groups have no item (-1).
+__device__ __forceinline__ int adj_item(int n_work) {
+  const int per = gridDim.x >> 3;
+  const int wi = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  return wi < n_work ? wi : -1;
+}
+
 __device__ __forceinline__ bool tile_node(const WorkItem &wk, int &i, int &j) {
   i = wk.x0 + (threadIdx.x & 31);
   j = wk.y0 + (threadIdx.x >> 5);
@@ -398,7 +407,9 @@ __device__ __forceinline__ void collide_recolour_vjp(const T f[9], T Fxi, T Fyi,
 // positions of the grid it clears the adjoint of C (the stress and stencil transposes add there).
 template <typename S, typename T>
 __global__ __launch_bounds__(kThreads) void adj_node(AdjArgs<S, T> A, int64_t tplane) {
-  const WorkItem wk = A.work[blockIdx.x];
+  const int wi = adj_item(A.n_work);
+  if (wi < 0) return;
+  const WorkItem wk = A.work[wi];
   const DomainDev &D = A.doms[wk.dom];
   int i, j;
   double graw[3] = {0, 0, 0};
@@ -504,7 +515,9 @@ __device__ __forceinline__ void pair_stress_vjp(const T cc[3], const T g[3][2], 
 // stress at z is gathered from their adjoint forces; the normals at z matter only at fluid nodes.
 template <typename S, typename T>
 __global__ __launch_bounds__(kThreads) void adj_stress(AdjArgs<S, T> A) {
-  const WorkItem wk = A.work[blockIdx.x];
+  const int wi = adj_item(A.n_work);
+  if (wi < 0) return;
+  const WorkItem wk = A.work[wi];
   const DomainDev &D = A.doms[wk.dom];
   int i, j;
   double sraw[3] = {0, 0, 0};
@@ -572,7 +585,9 @@ __global__ __launch_bounds__(kThreads) void adj_stress(AdjArgs<S, T> A) {
 // Adjoint of the colour-gradient stencil (Eq. 12).
 template <typename S, typename T>
 __global__ __launch_bounds__(kThreads) void adj_grad(AdjArgs<S, T> A) {
-  const WorkItem wk = A.work[blockIdx.x];
+  const int wi = adj_item(A.n_work);
+  if (wi < 0) return;
+  const WorkItem wk = A.work[wi];
   const DomainDev &D = A.doms[wk.dom];
   int i, j;
   if (!tile_node(wk, i, j)) return;
@@ -601,7 +616,9 @@ __global__ __launch_bounds__(kThreads) void adj_grad(AdjArgs<S, T> A) {
 // Adjoint of C_k = rho_k / rho, rho = sum_k rho_k at fluid nodes.
 template <typename S, typename T>
 __global__ __launch_bounds__(kThreads) void adj_comp(AdjArgs<S, T> A, int64_t tplane) {
-  const WorkItem wk = A.work[blockIdx.x];
+  const int wi = adj_item(A.n_work);
+  if (wi < 0) return;
+  const WorkItem wk = A.work[wi];
   const DomainDev &D = A.doms[wk.dom];
   int i, j;
   if (!tile_node(wk, i, j) || !fluid_node(A.flags, D, i, j)) return;
@@ -784,7 +801,7 @@ __global__ __launch_bounds__(kThreads) void adj_seed(const DomainDev *doms, cons
 // ---- launchers -----------------------------------------------------------------------------
 template <typename S, typename T>
 hipError_t launch_adjoint(const AdjArgs<S, T> &a, int64_t tplane, hipStream_t s) {
-  const dim3 g(a.n_work), b(kThreads);
+  const dim3 g((a.n_work + 7) / 8 * 8), b(kThreads);
   hipLaunchKernelGGL((adj_node<S, T>), g, b, 0, s, a, tplane);
   hipLaunchKernelGGL((adj_stress<S, T>), g, b, 0, s, a);
   hipLaunchKernelGGL((adj_grad<S, T>), g, b, 0, s, a);
