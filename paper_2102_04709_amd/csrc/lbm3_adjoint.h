@@ -35,6 +35,7 @@ struct AdjArgs {
   int n_work;
   const uint8_t *flags;
   const IbbNode *ibb;
+  const int32_t *ibb_of;  // per node of the state planes (D.base + plane index): its IbbNode index
   const FillNode *fill;
   int n_fill;
   const T *fillC;

@@ -212,14 +212,14 @@ __device__ __forceinline__ void stream_gather(const AdjArgs<S, T> &A, const Doma
       cmap(D, zi, zj);
       if (solid_at(A.flags, D, zi, zj)) {
         const int a = lat_opp(d);
-        const T qa = (T)find_ibb(A.ibb, D, yli)->q[a - 1];
+        const T qa = (T)A.ibb[A.ibb_of[D.base + yli]].q[a - 1];
         if (qa < T(0.5)) take(d, T(1) - T(2) * qa, Lf[a * P + yli], m0, m1, m2);
       }
     }
   }
   // own solid links
   const uint8_t fl = A.flags[D.base + li];
-  const IbbNode *ib = ((fl & FL_CURVED) && D.n_ibb > 0) ? find_ibb(A.ibb, D, li) : nullptr;
+  const IbbNode *ib = ((fl & FL_CURVED) && D.n_ibb > 0) ? A.ibb + A.ibb_of[D.base + li] : nullptr;
   const T mu0 = Lr[li], mu1 = Lr[P + li], mu2 = Lr[2 * P + li];
 #pragma unroll
   for (int a = 1; a < 9; ++a) {

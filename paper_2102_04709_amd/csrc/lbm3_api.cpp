@@ -68,7 +68,8 @@ struct DomHost {
 
 struct Layout {
   size_t off_F[2], off_R[2], off_flags, off_fill, off_fillC, off_ibb, off_doms, off_work, off_fwork, off_partial,
-      off_chunk_dom, off_chunk_first, off_mass, off_bad, off_aX, off_awork, off_raw, off_tibb, off_fblk, total;
+      off_chunk_dom, off_chunk_first, off_mass, off_bad, off_aX, off_awork, off_raw, off_tibb, off_fblk, off_ibbof,
+      total;
   int64_t total_plane;
   int64_t aplane;  // elements of one adjoint scratch plane (all domains' extended grids)
   int n_fill, n_ibb, n_chunks, max_work, n_fwork, n_awork, n_fblk;
@@ -439,11 +440,12 @@ bool plan(const lbm3_domain *d, int n, const lbm3_options *o, std::vector<DomHos
   L.off_chunk_first = take(sizeof(int) * (n + 1));
   L.off_mass = take(sizeof(double) * 3 * n);
   L.off_bad = take(sizeof(int));
-  L.off_aX = L.off_awork = L.off_raw = 0;
+  L.off_aX = L.off_awork = L.off_raw = L.off_ibbof = 0;
   if (o->adjoint) {
     L.off_aX = take((size_t)A_PLANES * (size_t)abase * t_size(prec));
     L.off_awork = take(sizeof(WorkItem) * naw);
     L.off_raw = take(sizeof(double) * 9 * n);
+    L.off_ibbof = take(sizeof(int32_t) * (size_t)base);
   }
   L.total = off;
   return true;
@@ -785,6 +787,7 @@ lbm3_status adjoint_step_t(lbm3_ctx *c, const void *state, const void *lin, void
   a.n_work = (int)c->awork.size();
   a.flags = c->at<uint8_t>(c->L.off_flags);
   a.ibb = c->at<IbbNode>(c->L.off_ibb);
+  a.ibb_of = c->at<int32_t>(c->L.off_ibbof);
   a.fill = c->at<FillNode>(c->L.off_fill);
   a.n_fill = c->L.n_fill;
   a.fillC = c->at<T>(c->L.off_fillC);
@@ -936,6 +939,13 @@ lbm3_status lbm3_create(const lbm3_domain *d, int32_t n, const lbm3_options *o, 
       fblk.push_back(FillBlock{i, H[i].dd.fill_off + f0, std::min(kFillNodes, H[i].dd.n_fill - f0), 0});
   if (!fblk.empty())
     CK(hipMemcpyAsync(c->at<void>(L.off_fblk), fblk.data(), sizeof(FillBlock) * fblk.size(), hipMemcpyHostToDevice, s));
+  std::vector<int32_t> ibb_of;  // adjoint only: index of each node's link record (-1: none)
+  if (c->adjoint) {
+    ibb_of.assign((size_t)L.total_plane, -1);
+    for (int i = 0; i < n; ++i)
+      for (int r = 0; r < H[i].dd.n_ibb; ++r) ibb_of[(size_t)(H[i].dd.base + ibb[H[i].dd.ibb_off + r].li)] = H[i].dd.ibb_off + r;
+    CK(hipMemcpyAsync(c->at<void>(L.off_ibbof), ibb_of.data(), sizeof(int32_t) * ibb_of.size(), hipMemcpyHostToDevice, s));
+  }
   CK(hipMemcpyAsync(c->at<void>(L.off_chunk_dom), chunk_dom.data(), sizeof(int) * chunk_dom.size(), hipMemcpyHostToDevice, s));
   CK(hipMemcpyAsync(c->at<void>(L.off_chunk_first), chunk_first.data(), sizeof(int) * chunk_first.size(), hipMemcpyHostToDevice, s));
   CK(hipMemsetAsync(c->at<void>(L.off_bad), 0, sizeof(int), s));
