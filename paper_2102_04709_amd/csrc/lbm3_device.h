@@ -65,9 +65,14 @@ __device__ __forceinline__ void store_nt<__half, float>(__half *p, float v) {
   __builtin_nontemporal_store(*reinterpret_cast<const unsigned short *>(&h), reinterpret_cast<unsigned short *>(p));
 }
 
+// v mod n for v near [0, n): one select for v within a period of the range (every stencil and
+// halo offset on domains of at least 3 nodes), a loop only beyond.
 __device__ __forceinline__ int wrap_small(int v, int n) {
-  while (v < 0) v += n;
-  while (v >= n) v -= n;
+  v = v < 0 ? v + n : (v >= n ? v - n : v);
+  if (v < 0 || v >= n) {
+    while (v < 0) v += n;
+    while (v >= n) v -= n;
+  }
   return v;
 }
 
