@@ -33,14 +33,14 @@ __device__ __forceinline__ int64_t aidx(const DomainDev &D, int i, int j) { retu
 // Node whose stored data a read at (i, j) sees (the forward's node_index): periodic axes wrap,
 // the Zou-He x axis clamps to the boundary columns, a non-periodic y axis to the off-grid rows.
 __device__ __forceinline__ void cmap(const DomainDev &D, int &i, int &j) {
-  i = D.bcx == BCX_ZOUHE ? min(max(i, 0), D.nx - 1) : wrap_small(i, D.nx);
-  j = D.yper ? wrap_small(j, D.ny) : min(max(j, -2), D.ny + 1);
+  i = D.bcx == BCX_ZOUHE ? min(max(i, 0), D.nx - 1) : wrap_near(i, D.nx);
+  j = D.yper ? wrap_near(j, D.ny) : min(max(j, -2), D.ny + 1);
 }
 // Position of the stress a divergence at (i, j) reads: periodic axes wrap; the stress at a
 // Zou-He ghost column or an off-grid row is its own value (computed there from clamped C).
 __device__ __forceinline__ void tmap(const DomainDev &D, int &i, int &j) {
-  if (D.bcx != BCX_ZOUHE) i = wrap_small(i, D.nx);
-  if (D.yper) j = wrap_small(j, D.ny);
+  if (D.bcx != BCX_ZOUHE) i = wrap_near(i, D.nx);
+  if (D.yper) j = wrap_near(j, D.ny);
 }
 // Solid test of a mapped node (rows -2..ny+1 of the flag plane exist).
 __device__ __forceinline__ bool solid_at(const uint8_t *flags, const DomainDev &D, int i, int j) {
@@ -529,8 +529,8 @@ __global__ __launch_bounds__(kThreads) void adj_stress(AdjArgs<S, T> A) {
     for (int a = 1; a < 9; ++a) {
       const int ex = lat_ex(a), ey = lat_ey(a);
       int yi = i - ex, yj = j - ey;
-      if (D.bcx != BCX_ZOUHE) yi = wrap_small(yi, D.nx);
-      if (D.yper) yj = wrap_small(yj, D.ny);
+      if (D.bcx != BCX_ZOUHE) yi = wrap_near(yi, D.nx);
+      if (D.yper) yj = wrap_near(yj, D.ny);
       if (!fluid_node(A.flags, D, yi, yj)) continue;
       const int64_t y = aidx(D, yi, yj);
       const T lx = A.X[AL_F * AP + y], ly = A.X[(AL_F + 1) * AP + y];
