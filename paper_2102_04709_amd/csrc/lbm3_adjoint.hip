@@ -164,6 +164,7 @@ __device__ __forceinline__ void stream_gather(const AdjArgs<S, T> &A, const Doma
   const T *Lr = A.lin + 9 * tplane + 3 * D.base;
   const bool zh = D.bcx == BCX_ZOUHE;
   const T C[3] = {A.X[AX_C * AP + q], A.X[(AX_C + 1) * AP + q], A.X[(AX_C + 2) * AP + q]};
+  const uint32_t lk = A.links[D.base + li];
 #pragma unroll
   for (int c = 0; c < 13; ++c) lP[c] = T(0);
 #pragma unroll
@@ -193,9 +194,9 @@ __device__ __forceinline__ void stream_gather(const AdjArgs<S, T> &A, const Doma
     const int ex = lat_ex(d), ey = lat_ey(d);
     const int yx = i + ex;
     if (zh && (yx < 0 || yx >= D.nx)) continue;  // nothing is pulled out through a Zou-He boundary
+    if ((lk >> d) & 1) continue;
     int yi = yx, yj = j + ey;
     cmap(D, yi, yj);
-    if (solid_at(A.flags, D, yi, yj)) continue;
     const int64_t yli = plane_index(yi, yj, D.pitch);
     T lfv = Lf[d * P + yli];
     const T m0 = Lr[yli], m1 = Lr[P + yli], m2 = Lr[2 * P + yli];
@@ -207,10 +208,8 @@ __device__ __forceinline__ void stream_gather(const AdjArgs<S, T> &A, const Doma
     const bool crossed = D.bcx == BCX_SWAP13 && (yx < 0 || yx >= D.nx);
     if (crossed) take(d, T(1), lfv, m2, m1, m0);
     else take(d, T(1), lfv, m0, m1, m2);
-    if (d != 0 && (A.flags[D.base + yli] & FL_CURVED) && D.n_ibb > 0) {
-      int zi = yx + ex, zj = j + 2 * ey;
-      cmap(D, zi, zj);
-      if (solid_at(A.flags, D, zi, zj)) {
+    if (d != 0 && ((lk >> (9 + d)) & 1) && D.n_ibb > 0) {
+      if ((lk >> (18 + d)) & 1) {
         const int a = lat_opp(d);
         const T qa = (T)A.ibb[A.ibb_of[D.base + yli]].q[a - 1];
         if (qa < T(0.5)) take(d, T(1) - T(2) * qa, Lf[a * P + yli], m0, m1, m2);
@@ -218,23 +217,18 @@ __device__ __forceinline__ void stream_gather(const AdjArgs<S, T> &A, const Doma
     }
   }
   // own solid links
-  const uint8_t fl = A.flags[D.base + li];
-  const IbbNode *ib = ((fl & FL_CURVED) && D.n_ibb > 0) ? A.ibb + A.ibb_of[D.base + li] : nullptr;
+  const IbbNode *ib = (((lk >> 27) & 1) && D.n_ibb > 0) ? A.ibb + A.ibb_of[D.base + li] : nullptr;
   const T mu0 = Lr[li], mu1 = Lr[P + li], mu2 = Lr[2 * P + li];
 #pragma unroll
   for (int a = 1; a < 9; ++a) {
     const int ex = lat_ex(a), ey = lat_ey(a);
     const int sx = i - ex;
     if (zh && (sx < 0 || sx >= D.nx)) continue;
-    int si = sx, sj = j - ey;
-    cmap(D, si, sj);
-    if (!solid_at(A.flags, D, si, sj)) continue;
     const int ab = lat_opp(a);
+    if (!((lk >> ab) & 1)) continue;  // the node read at x - e_a is fluid
     const T qd = ib ? (T)ib->q[a - 1] : T(0.5);
     const T lfa = Lf[a * P + li];
-    int ni = i + ex, nj = j + ey;
-    cmap(D, ni, nj);
-    if (qd < T(0.5) && !solid_at(A.flags, D, ni, nj)) {
+    if (qd < T(0.5) && !((lk >> a) & 1)) {
       take(ab, T(2) * qd, lfa, mu0, mu1, mu2);  // the neighbour's share is gathered there
     } else if (qd < T(0.5)) {
       take(ab, T(1), lfa, mu0, mu1, mu2);

@@ -69,7 +69,7 @@ struct DomHost {
 struct Layout {
   size_t off_F[2], off_R[2], off_flags, off_fill, off_fillC, off_ibb, off_doms, off_work, off_fwork, off_partial,
       off_chunk_dom, off_chunk_first, off_mass, off_bad, off_aX, off_awork, off_raw, off_tibb, off_fblk, off_ibbof,
-      total;
+      off_links, total;
   int64_t total_plane;
   int64_t aplane;  // elements of one adjoint scratch plane (all domains' extended grids)
   int n_fill, n_ibb, n_chunks, max_work, n_fwork, n_awork, n_fblk;
@@ -440,12 +440,13 @@ bool plan(const lbm3_domain *d, int n, const lbm3_options *o, std::vector<DomHos
   L.off_chunk_first = take(sizeof(int) * (n + 1));
   L.off_mass = take(sizeof(double) * 3 * n);
   L.off_bad = take(sizeof(int));
-  L.off_aX = L.off_awork = L.off_raw = L.off_ibbof = 0;
+  L.off_aX = L.off_awork = L.off_raw = L.off_ibbof = L.off_links = 0;
   if (o->adjoint) {
     L.off_aX = take((size_t)A_PLANES * (size_t)abase * t_size(prec));
     L.off_awork = take(sizeof(WorkItem) * naw);
     L.off_raw = take(sizeof(double) * 9 * n);
     L.off_ibbof = take(sizeof(int32_t) * (size_t)base);
+    L.off_links = take(sizeof(uint32_t) * (size_t)base);
   }
   L.total = off;
   return true;
@@ -788,6 +789,7 @@ lbm3_status adjoint_step_t(lbm3_ctx *c, const void *state, const void *lin, void
   a.flags = c->at<uint8_t>(c->L.off_flags);
   a.ibb = c->at<IbbNode>(c->L.off_ibb);
   a.ibb_of = c->at<int32_t>(c->L.off_ibbof);
+  a.links = c->at<uint32_t>(c->L.off_links);
   a.fill = c->at<FillNode>(c->L.off_fill);
   a.n_fill = c->L.n_fill;
   a.fillC = c->at<T>(c->L.off_fillC);
@@ -945,6 +947,33 @@ lbm3_status lbm3_create(const lbm3_domain *d, int32_t n, const lbm3_options *o, 
     for (int i = 0; i < n; ++i)
       for (int r = 0; r < H[i].dd.n_ibb; ++r) ibb_of[(size_t)(H[i].dd.base + ibb[H[i].dd.ibb_off + r].li)] = H[i].dd.ibb_off + r;
     CK(hipMemcpyAsync(c->at<void>(L.off_ibbof), ibb_of.data(), sizeof(int32_t) * ibb_of.size(), hipMemcpyHostToDevice, s));
+  }
+  std::vector<uint32_t> links;  // adjoint only: the link bits of every fluid node (AdjArgs::links)
+  if (c->adjoint) {
+    links.assign((size_t)L.total_plane, 0u);
+    for (int dd = 0; dd < n; ++dd) {
+      const DomainDev &D = H[dd].dd;
+      const uint8_t *fl = H[dd].flags.data();
+      auto mapped = [&](int i, int j) -> uint8_t {  // flags of the node a read at (i, j) sees
+        i = D.bcx == BCX_ZOUHE ? std::min(std::max(i, 0), D.nx - 1) : ((i % D.nx) + D.nx) % D.nx;
+        j = D.yper ? ((j % D.ny) + D.ny) % D.ny : std::min(std::max(j, -2), D.ny + 1);
+        return fl[plane_index(i, j, D.pitch)];
+      };
+      for (int j = 0; j < D.ny; ++j)
+        for (int i = 0; i < D.nx; ++i) {
+          const int64_t li = plane_index(i, j, D.pitch);
+          if (fl[li] & FL_SOLID) continue;
+          uint32_t b = (fl[li] & FL_CURVED) ? (1u << 27) : 0u;
+          for (int d = 0; d < 9; ++d) {
+            const uint8_t f1 = mapped(i + kEX[d], j + kEY[d]), f2 = mapped(i + 2 * kEX[d], j + 2 * kEY[d]);
+            if (f1 & FL_SOLID) b |= 1u << d;
+            if (f1 & FL_CURVED) b |= 1u << (9 + d);
+            if (f2 & FL_SOLID) b |= 1u << (18 + d);
+          }
+          links[(size_t)(D.base + li)] = b;
+        }
+    }
+    CK(hipMemcpyAsync(c->at<void>(L.off_links), links.data(), sizeof(uint32_t) * links.size(), hipMemcpyHostToDevice, s));
   }
   CK(hipMemcpyAsync(c->at<void>(L.off_chunk_dom), chunk_dom.data(), sizeof(int) * chunk_dom.size(), hipMemcpyHostToDevice, s));
   CK(hipMemcpyAsync(c->at<void>(L.off_chunk_first), chunk_first.data(), sizeof(int) * chunk_first.size(), hipMemcpyHostToDevice, s));
