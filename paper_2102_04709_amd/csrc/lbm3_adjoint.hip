@@ -86,6 +86,11 @@ __device__ __forceinline__ int adj_item(int n_work) {
   return wi < n_work ? wi : -1;
 }
 
+// The adjoint kernels' tiles are 32 x 8 nodes, one per thread of a 256-thread work-group; the
+// node kernel stages lambda_{t+1} of the tile + 1 ring in LDS.
+constexpr int kAdjTX = 32, kAdjTY = 8, kAdjW1 = kAdjTX + 2, kAdjN1 = kAdjW1 * (kAdjTY + 2);
+static_assert(kAdjTX * kAdjTY == kThreads, "one adjoint tile node per thread");
+
 __device__ __forceinline__ bool tile_node(const WorkItem &wk, int &i, int &j) {
   i = wk.x0 + (threadIdx.x & 31);
   j = wk.y0 + (threadIdx.x >> 5);
@@ -155,7 +160,10 @@ __device__ __forceinline__ T zh_add(const DomainDev &D, bool inlet, int d, const
 // collision transpose to them at once (adj_node).
 template <typename S, typename T>
 __device__ __forceinline__ void stream_gather(const AdjArgs<S, T> &A, const DomainDev &D, int i, int j, int64_t tplane,
-                                              const T fp[9], T lP[13], T lC[3]) {
+                                              const T fp[9], const T (*sL)[kAdjN1], T lP[13], T lC[3]) {
+  // sL[c][p]: lambda_{t+1} (9 distributions, 3 densities) of the node read at tile position p of the
+  // ring-1 block; the node itself is at p0
+  const int p0 = (int)(threadIdx.x & (kAdjTX - 1)) + 1 + ((int)(threadIdx.x / kAdjTX) + 1) * kAdjW1;
   const int64_t AP = A.aplane;
   const int64_t P = D.plane;
   const int64_t li = plane_index(i, j, D.pitch);
@@ -198,8 +206,9 @@ __device__ __forceinline__ void stream_gather(const AdjArgs<S, T> &A, const Doma
     int yi = yx, yj = j + ey;
     cmap(D, yi, yj);
     const int64_t yli = plane_index(yi, yj, D.pitch);
-    T lfv = Lf[d * P + yli];
-    const T m0 = Lr[yli], m1 = Lr[P + yli], m2 = Lr[2 * P + yli];
+    const int py = p0 + ex + ey * kAdjW1;
+    T lfv = sL[d][py];
+    const T m0 = sL[9][py], m1 = sL[10][py], m2 = sL[11][py];
     if (zh && (yi == 0 || yi == D.nx - 1)) {
       const int64_t yq = aidx(D, yi, yj);
       const T Cy[3] = {A.X[AX_C * AP + yq], A.X[(AX_C + 1) * AP + yq], A.X[(AX_C + 2) * AP + yq]};
@@ -212,13 +221,13 @@ __device__ __forceinline__ void stream_gather(const AdjArgs<S, T> &A, const Doma
       if ((lk >> (18 + d)) & 1) {
         const int a = lat_opp(d);
         const T qa = (T)A.ibb[A.ibb_of[D.base + yli]].q[a - 1];
-        if (qa < T(0.5)) take(d, T(1) - T(2) * qa, Lf[a * P + yli], m0, m1, m2);
+        if (qa < T(0.5)) take(d, T(1) - T(2) * qa, sL[a][py], m0, m1, m2);
       }
     }
   }
   // own solid links
   const IbbNode *ib = (((lk >> 27) & 1) && D.n_ibb > 0) ? A.ibb + A.ibb_of[D.base + li] : nullptr;
-  const T mu0 = Lr[li], mu1 = Lr[P + li], mu2 = Lr[2 * P + li];
+  const T mu0 = sL[9][p0], mu1 = sL[10][p0], mu2 = sL[11][p0];
 #pragma unroll
   for (int a = 1; a < 9; ++a) {
     const int ex = lat_ex(a), ey = lat_ey(a);
@@ -227,7 +236,7 @@ __device__ __forceinline__ void stream_gather(const AdjArgs<S, T> &A, const Doma
     const int ab = lat_opp(a);
     if (!((lk >> ab) & 1)) continue;  // the node read at x - e_a is fluid
     const T qd = ib ? (T)ib->q[a - 1] : T(0.5);
-    const T lfa = Lf[a * P + li];
+    const T lfa = sL[a][p0];
     if (qd < T(0.5) && !((lk >> a) & 1)) {
       take(ab, T(2) * qd, lfa, mu0, mu1, mu2);  // the neighbour's share is gathered there
     } else if (qd < T(0.5)) {
@@ -401,6 +410,7 @@ __device__ __forceinline__ void collide_recolour_vjp(const T f[9], T Fxi, T Fyi,
 // positions of the grid it clears the adjoint of C (the stress and stencil transposes add there).
 template <typename S, typename T>
 __global__ __launch_bounds__(kThreads) void adj_node(AdjArgs<S, T> A, int64_t tplane) {
+  __shared__ T sL[12][kAdjN1];
   const int wi = adj_item(A.n_work);
   if (wi < 0) return;
   const WorkItem wk = A.work[wi];
@@ -408,6 +418,21 @@ __global__ __launch_bounds__(kThreads) void adj_node(AdjArgs<S, T> A, int64_t tp
   int i, j;
   double graw[3] = {0, 0, 0};
   const int64_t AP = A.aplane;
+  {  // lambda_{t+1} of the tile + 1 ring, at the nodes the reads there see
+    const T *Lf = A.lin + 9 * D.base;
+    const T *Lr = A.lin + 9 * tplane + 3 * D.base;
+    for (int p = threadIdx.x; p < kAdjN1; p += kThreads) {
+      int gi = wk.x0 - 1 + p % kAdjW1, gj = wk.y0 - 1 + p / kAdjW1;
+      if (gi > wk.x1 || gj > wk.y1) continue;  // beyond the ring of a partial tile (never read)
+      cmap(D, gi, gj);
+      const int64_t gl = plane_index(gi, gj, D.pitch);
+#pragma unroll
+      for (int c = 0; c < 9; ++c) sL[c][p] = Lf[c * D.plane + gl];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) sL[9 + c][p] = Lr[c * D.plane + gl];
+    }
+  }
+  __syncthreads();
   if (tile_node(wk, i, j) && i >= 0 && i < D.nx) {
     const int64_t q = aidx(D, i, j);
     if (!fluid_node(A.flags, D, i, j)) {
@@ -428,7 +453,7 @@ __global__ __launch_bounds__(kThreads) void adj_node(AdjArgs<S, T> A, int64_t tp
         collide_shifted(f, Fx, Fy, C[0] * rt, C[1] * rt, C[2] * rt, K, fd, ux, uy);
       }
       T lP[13], lCs[3];
-      stream_gather(A, D, i, j, tplane, fd, lP, lCs);
+      stream_gather(A, D, i, j, tplane, fd, sL, lP, lCs);
 #pragma unroll
       for (int c = 0; c < 6; ++c) nrm[c] = A.X[(AX_N + c) * AP + q];
       T lf[9], lFx, lFy, lC[3], lrt, ln[6], lgX[3];
