@@ -534,25 +534,46 @@ __device__ __forceinline__ void pair_stress_vjp(const T cc[3], const T g[3][2], 
 // stress at z is gathered from their adjoint forces; the normals at z matter only at fluid nodes.
 template <typename S, typename T>
 __global__ __launch_bounds__(kThreads) void adj_stress(AdjArgs<S, T> A) {
+  __shared__ T sC[3][kAdjN1];       // C_k at the nodes the ring-1 block's reads see
+  __shared__ T sF[2][kAdjN1];       // adjoint force at the block's (wrapped) positions, fluid only
+  __shared__ uint8_t sFl[kAdjN1];   // whether that position is a fluid node
   const int wi = adj_item(A.n_work);
   if (wi < 0) return;
   const WorkItem wk = A.work[wi];
   const DomainDev &D = A.doms[wk.dom];
+  const int64_t AP = A.aplane;
+  for (int p = threadIdx.x; p < kAdjN1; p += kThreads) {
+    const int gi = wk.x0 - 1 + p % kAdjW1, gj = wk.y0 - 1 + p / kAdjW1;
+    if (gi > wk.x1 || gj > wk.y1) continue;  // beyond the ring of a partial tile (never read)
+    int ci = gi, cj = gj;
+    cmap(D, ci, cj);
+    const int64_t qc = aidx(D, ci, cj);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) sC[k][p] = A.X[(AX_C + k) * AP + qc];
+    int yi = gi, yj = gj;
+    if (D.bcx != BCX_ZOUHE) yi = wrap_near(yi, D.nx);
+    if (D.yper) yj = wrap_near(yj, D.ny);
+    const bool fl = fluid_node(A.flags, D, yi, yj);
+    sFl[p] = fl;
+    if (fl) {
+      const int64_t y = aidx(D, yi, yj);
+      sF[0][p] = A.X[AL_F * AP + y];
+      sF[1][p] = A.X[(AL_F + 1) * AP + y];
+    }
+  }
+  __syncthreads();
+  const int p0 = (int)(threadIdx.x & (kAdjTX - 1)) + 1 + ((int)(threadIdx.x / kAdjTX) + 1) * kAdjW1;
   int i, j;
   double sraw[3] = {0, 0, 0};
   if (tile_node(wk, i, j)) {
-    const int64_t AP = A.aplane;
     const int64_t q = aidx(D, i, j);
     T lt[3] = {T(0), T(0), T(0)}, ln[6];
 #pragma unroll
     for (int a = 1; a < 9; ++a) {
       const int ex = lat_ex(a), ey = lat_ey(a);
-      int yi = i - ex, yj = j - ey;
-      if (D.bcx != BCX_ZOUHE) yi = wrap_near(yi, D.nx);
-      if (D.yper) yj = wrap_near(yj, D.ny);
-      if (!fluid_node(A.flags, D, yi, yj)) continue;
-      const int64_t y = aidx(D, yi, yj);
-      const T lx = A.X[AL_F * AP + y], ly = A.X[(AL_F + 1) * AP + y];
+      const int py = p0 - ex - ey * kAdjW1;  // y = z - e_a
+      if (!sFl[py]) continue;
+      const T lx = sF[0][py], ly = sF[1][py];
       const T c = T(3) * wgt<T>(a);
       lt[0] += c * T(ex) * lx;
       lt[1] += c * (T(ey) * lx + T(ex) * ly);
@@ -575,11 +596,12 @@ __global__ __launch_bounds__(kThreads) void adj_stress(AdjArgs<S, T> A) {
       const int64_t qc = aidx(D, ci, cj);
       T cc[3], g[3][2];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) cc[c] = A.X[(AX_C + c) * AP + qc];
+      for (int c = 0; c < 3; ++c) cc[c] = sC[c][p0];
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         T c9[9];
-        c9_at(A.X, AP, D, i, j, k, c9);
+#pragma unroll
+        for (int a = 0; a < 9; ++a) c9[a] = sC[k][p0 + lat_ex(a) + lat_ey(a) * kAdjW1];
         grad9(c9, g[k][0], g[k][1]);
       }
       const T rho = A.X[(AX_C + 3) * AP + qc];
