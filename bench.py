@@ -29,21 +29,21 @@ HBM_PEAK_GBS = 8000.0
 # precision and kernel configuration, valid for the kernel sources with the given digest only.
 KERNEL_SOURCES = ("lbm3_kernels.hip", "lbm3_device.h", "lbm3_internal.h", "lbm3_kernels.h", "lbm3_adjoint.h")
 TRAFFIC = {
-    "digest": "8d0042cee01efeea",
+    "digest": "7098a4cf44893479",
     ('cylinder_janus', 400, 'f32', (0, 16, 16)): (4490.5 * 2.0 + 6969.0 * 1.0) * 1024,
     ('cylinder_janus', 400, 'f32', (3, 16, 16)): (4872.2 * 2.0 + 8219.0 * 1.0) * 1024,
     ('cylinder_janus', 400, 'f32', (0, 32, 8)): (4368.8 * 2.0 + 6969.0 * 1.0) * 1024,
     ('cylinder_janus', 400, 'f32', (3, 32, 16)): (4484.3 * 2.0 + 6969.0 * 1.0) * 1024,
     ('cylinder_janus', 400, 'f32', (3, 64, 8)): (4358.1 * 2.0 + 6969.0 * 1.0) * 1024,
     ('cylinder_janus', 400, 'f32', (0, 64, 4)): (4290.8 * 2.0 + 6969.0 * 1.0) * 1024,
-    ('cylinder_janus', 400, 'f32', (0, 64, 8)): (6477.6 * 2.0 + 12219.0 * 1.0) * 1024,
-    ('cylinder_janus', 400, 'f32', (1, 0, 32)): (4649.1 * 2.0 + 7549.9 * 1.0) * 1024,
-    ('cylinder_janus', 400, 'f32', (2, 0, 32)): (4133.6 * 2.0 + 7469.7 * 1.0) * 1024,
-    ('cylinder_janus', 400, 'f32', (2, 0, 64)): (4133.6 * 2.0 + 7358.7 * 1.0) * 1024,
-    ('cylinder_janus_x10', 4000, 'f32', (0, 32, 8)): (363873.4 * 2.0 + 696999.1 * 1.0) * 1024,
-    ('cylinder_janus_x10', 4000, 'f32', (0, 16, 16)): (428398.1 * 2.0 + 700091.0 * 1.0) * 1024,
-    ('cylinder_janus_x10', 4000, 'f32', (3, 64, 8)): (362915.2 * 2.0 + 696999.1 * 1.0) * 1024,
-    ('cylinder_janus_x10', 4000, 'f32', (3, 32, 16)): (372366.8 * 2.0 + 696999.6 * 1.0) * 1024,
+    ('cylinder_janus', 400, 'f32', (0, 64, 8)): (6476.9 * 2.0 + 12219.0 * 1.0) * 1024,
+    ('cylinder_janus', 400, 'f32', (1, 0, 32)): (4649.1 * 2.0 + 7543.4 * 1.0) * 1024,
+    ('cylinder_janus', 400, 'f32', (2, 0, 32)): (4133.6 * 2.0 + 7471.0 * 1.0) * 1024,
+    ('cylinder_janus', 400, 'f32', (2, 0, 64)): (4133.6 * 2.0 + 7369.2 * 1.0) * 1024,
+    ('cylinder_janus_x10', 4000, 'f32', (0, 32, 8)): (363842.6 * 2.0 + 696999.2 * 1.0) * 1024,
+    ('cylinder_janus_x10', 4000, 'f32', (0, 16, 16)): (429336.2 * 2.0 + 699735.1 * 1.0) * 1024,
+    ('cylinder_janus_x10', 4000, 'f32', (3, 64, 8)): (362889.4 * 2.0 + 696999.2 * 1.0) * 1024,
+    ('cylinder_janus_x10', 4000, 'f32', (3, 32, 16)): (372423.7 * 2.0 + 696999.7 * 1.0) * 1024,
 }
 
 

@@ -73,15 +73,16 @@ __device__ __forceinline__ int wrap_small(int v, int n) {
 }
 
 // v mod n for v in [-n, 2n): the stencil and halo offsets (at most 3) on axes of at least 3 nodes,
-// which lbm3_create requires.  One select instead of a loop.
+// which lbm3_create requires.  One select instead of a loop (the adjoint's kernels; in the fused
+// step kernel the loop form gives the better register allocation).
 __device__ __forceinline__ int wrap_near(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
 // Index of node (gx, gy) within the domain's plane: periodic axes wrap, the Zou-He x axis
 // clamps to the boundary columns (zero-gradient ghost columns), a non-periodic y axis clamps to
 // the two off-grid solid rows.
 __device__ __forceinline__ int64_t node_index(int gx, int gy, const DomainDev &D) {
-  gx = D.bcx == BCX_ZOUHE ? min(max(gx, 0), D.nx - 1) : wrap_near(gx, D.nx);
-  gy = D.yper ? wrap_near(gy, D.ny) : min(max(gy, -2), D.ny + 1);
+  gx = D.bcx == BCX_ZOUHE ? min(max(gx, 0), D.nx - 1) : wrap_small(gx, D.nx);
+  gy = D.yper ? wrap_small(gy, D.ny) : min(max(gy, -2), D.ny + 1);
   return plane_index(gx, gy, D.pitch);
 }
 

@@ -392,13 +392,13 @@ __global__ __launch_bounds__(NT) void step_strip(StepArgs<S, T> A) {
     const int64_t P = D.plane;
     const KT<T> K = make_kt<T>(D);
     const int gx = x0 - 3 + c;
-    const int gxm = D.bcx == BCX_ZOUHE ? min(max(gx, 0), D.nx - 1) : wrap_near(gx, D.nx);
+    const int gxm = D.bcx == BCX_ZOUHE ? min(max(gx, 0), D.nx - 1) : wrap_small(gx, D.nx);
     const int yend = min(y1, D.ny);
 
     for (int r = y0 - 3; r <= y1 + 2; ++r) {
       // Stage A: C_k and rho of row r.
       {
-        const int gy = D.yper ? wrap_near(r, D.ny) : min(max(r, -2), D.ny + 1);
+        const int gy = D.yper ? wrap_small(r, D.ny) : min(max(r, -2), D.ny + 1);
         const int64_t li = plane_index(gxm, gy, D.pitch);
         const uint8_t fl = flags[li];
         T v[4];
@@ -460,7 +460,7 @@ __global__ __launch_bounds__(NT) void step_strip(StepArgs<S, T> A) {
           const T rt = mi[3 * NT];
           T txx, txy, tyy, nrm[6];
           pair_stress(cc, g, rt, K, eps_g, txx, txy, tyy, nrm);
-          const int gy = D.yper ? wrap_near(yc, D.ny) : yc;
+          const int gy = D.yper ? wrap_small(yc, D.ny) : yc;
           const int64_t li = plane_index(gxm, gy, D.pitch);
           T f[9];
 #pragma unroll
