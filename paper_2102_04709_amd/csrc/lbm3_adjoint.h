@@ -35,6 +35,7 @@ struct AdjArgs {
   int n_work;
   const uint8_t *flags;
   const IbbNode *ibb;
+  const uint32_t *far;    // [kFarW * n_fill] far fluid masks of the fill nodes
   const int32_t *ibb_of;  // per node of the state planes (D.base + plane index): its IbbNode index
   // per fluid node of the state planes: bit d = the node read at x + e_d is solid, bit 9 + d = it
   // has curved links, bit 18 + d = the node read at x + 2 e_d is solid, bit 27 = x has curved links

@@ -687,10 +687,18 @@ __global__ __launch_bounds__(kThreads) void adj_comp(AdjArgs<S, T> A, int64_t tp
 // are added atomically to the density adjoint and to the parameter partials.
 template <typename S, typename T>
 __global__ __launch_bounds__(kThreads) void adj_fill(AdjArgs<S, T> A, int64_t tplane) {
+  __shared__ uint32_t far[kThreads / 4][kFarW];  // the nodes' far fluid masks
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
   const int idx = gid >> 2, line = gid & 3, k = line >> 1;
   const bool active = idx < A.n_fill;
   const FillNode fn = A.fill[active ? idx : 0];
+  constexpr int kFarPerLane = (kFarW + 3) / 4;
+  uint32_t fr[kFarPerLane];  // loaded with the node, stored to LDS once the adjoint of C is in
+#pragma unroll
+  for (int c = 0; c < kFarPerLane; ++c) {
+    const int e = line + 4 * c;
+    fr[c] = e < kFarW ? A.far[(size_t)(active ? idx : 0) * kFarW + e] : 0u;
+  }
   const DomainDev &D = A.doms[fn.dom];
   const int64_t AP = A.aplane;
   const int64_t P = D.plane;
@@ -703,6 +711,10 @@ __global__ __launch_bounds__(kThreads) void adj_fill(AdjArgs<S, T> A, int64_t tp
     lam = (double)A.X[(AL_C + k) * AP + qa] - (double)A.X[(AL_C + 2) * AP + qa];
   }
   const bool work = active && lam != 0.0;  // equal in the two lanes of a fluid
+#pragma unroll
+  for (int c = 0; c < kFarPerLane; ++c)
+    if (line + 4 * c < kFarW) far[threadIdx.x >> 2][line + 4 * c] = fr[c];
+  __syncthreads();
   auto fluid_at = [&](int i, int j) -> bool {
     const int dx = i - fn.i, dy = j - fn.j;
     if (FluidMask::inside(dx, dy)) return fn.mask.fluid(dx, dy);
@@ -749,7 +761,7 @@ __global__ __launch_bounds__(kThreads) void adj_fill(AdjArgs<S, T> A, int64_t tp
     sincos_quadrant(phi, sn, cs);
     const double sg = (line & 1) ? -1.0 : 1.0;
     const double dx = cs * fn.nx - sg * sn * fn.ny, dy = cs * fn.ny + sg * sn * fn.nx;
-    const LineHit h = march_line_masked(fn.i, fn.j, dx, dy, fn.mask, fluid_at);
+    const LineHit h = march_line_masked(fn.i, fn.j, dx, dy, fn.mask, far[threadIdx.x >> 2], fluid_at);
     if (h.ok) {
       ok = 1;
       n0 = node_q(h.i0, h.j0);

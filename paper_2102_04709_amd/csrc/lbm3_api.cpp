@@ -63,13 +63,14 @@ struct DomHost {
   DomainDev dd;
   std::vector<uint8_t> flags;   // [(ny+4) * pitch]
   std::vector<FillNode> fill;
+  std::vector<uint32_t> far;    // kFarW rows per fill node: its far fluid mask
   std::vector<IbbNode> ibb;
 };
 
 struct Layout {
   size_t off_F[2], off_R[2], off_flags, off_fill, off_fillC, off_ibb, off_doms, off_work, off_fwork, off_partial,
       off_chunk_dom, off_chunk_first, off_mass, off_bad, off_aX, off_awork, off_raw, off_tibb, off_fblk, off_ibbof,
-      off_links, total;
+      off_links, off_far, total;
   int64_t total_plane;
   int64_t aplane;  // elements of one adjoint scratch plane (all domains' extended grids)
   int n_fill, n_ibb, n_chunks, max_work, n_fwork, n_awork, n_fblk;
@@ -305,6 +306,12 @@ bool validate_and_build(const lbm3_domain &d, int dom, double beta0, DomHost &H,
         for (int dy = -kMaskR; dy <= kMaskR; ++dy)
           for (int dx = -kMaskR; dx <= kMaskR; ++dx)
             if (fluid_at(i + dx, j + dy)) fn.mask.set(dx, dy);
+        for (int dy = -kFarR; dy <= kFarR; ++dy) {
+          uint32_t row = 0;
+          for (int dx = -kFarR; dx <= kFarR; ++dx)
+            if (fluid_at(i + dx, j + dy)) row |= 1u << (dx + kFarR);
+          H.far.push_back(row);
+        }
         H.flags[p] |= FL_FILL;
         H.fill.push_back(fn);
       }
@@ -431,6 +438,7 @@ bool plan(const lbm3_domain *d, int n, const lbm3_options *o, std::vector<DomHos
   L.off_fillC = take(3 * t_size(prec) * std::max(nf, 1));
   L.off_tibb = take(sizeof(TileIbb) * std::max(ni, 1));
   L.off_fblk = take(sizeof(FillBlock) * std::max(nfb, 1));
+  L.off_far = take(sizeof(uint32_t) * kFarW * (size_t)std::max(nf, 1));
   L.off_ibb = take(sizeof(IbbNode) * std::max(ni, 1));
   L.off_doms = take(sizeof(DomainDev) * n);
   L.off_work = take(sizeof(WorkItem) * maxw);
@@ -638,6 +646,7 @@ FillArgs<T> fill_args(lbm3_ctx *c, int which) {
   f.n_fill = c->L.n_fill;
   f.blocks = c->at<FillBlock>(c->L.off_fblk);
   f.n_blocks = c->L.n_fblk;
+  f.far = c->at<uint32_t>(c->L.off_far);
   f.doms = c->at<DomainDev>(c->L.off_doms);
   f.flags = c->at<uint8_t>(c->L.off_flags);
   f.rho = c->at<T>(c->L.off_R[which]);
@@ -789,6 +798,7 @@ lbm3_status adjoint_step_t(lbm3_ctx *c, const void *state, const void *lin, void
   a.flags = c->at<uint8_t>(c->L.off_flags);
   a.ibb = c->at<IbbNode>(c->L.off_ibb);
   a.ibb_of = c->at<int32_t>(c->L.off_ibbof);
+  a.far = c->at<uint32_t>(c->L.off_far);
   a.links = c->at<uint32_t>(c->L.off_links);
   a.fill = c->at<FillNode>(c->L.off_fill);
   a.n_fill = c->L.n_fill;
@@ -935,6 +945,13 @@ lbm3_status lbm3_create(const lbm3_domain *d, int32_t n, const lbm3_options *o, 
   CK(hipMemcpyAsync(c->at<void>(L.off_flags), flags.data(), flags.size(), hipMemcpyHostToDevice, s));
   if (!fill.empty()) CK(hipMemcpyAsync(c->at<void>(L.off_fill), fill.data(), sizeof(FillNode) * fill.size(), hipMemcpyHostToDevice, s));
   if (!ibb.empty()) CK(hipMemcpyAsync(c->at<void>(L.off_ibb), ibb.data(), sizeof(IbbNode) * ibb.size(), hipMemcpyHostToDevice, s));
+  {
+    std::vector<uint32_t> far;  // far fluid masks of all fill nodes, in fill order
+    for (int i = 0; i < n; ++i) far.insert(far.end(), H[i].far.begin(), H[i].far.end());
+    if (!far.empty())
+      CK(hipMemcpyAsync(c->at<void>(L.off_far), far.data(), sizeof(uint32_t) * far.size(), hipMemcpyHostToDevice, s));
+    CK(hipStreamSynchronize(s));
+  }
   std::vector<FillBlock> fblk;  // work-groups of the fill kernel: up to kFillNodes nodes of one domain
   for (int i = 0; i < n; ++i)
     for (int f0 = 0; f0 < H[i].dd.n_fill; f0 += kFillNodes)

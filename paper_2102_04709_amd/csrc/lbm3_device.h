@@ -101,10 +101,12 @@ __device__ __forceinline__ double cfrac_at(const T *r, int64_t P, int64_t q, int
 // Lane `line` (0..3) of the four lanes that fill one node: fluid k = line / 2, side
 // s = line % 2.  Every lane forms C at D0 and the angle of its fluid, marches its line and
 // interpolates; the lanes of a fluid then combine their values with Eq. (22) and lane 0
-// receives the second fluid's value.  Returns (C1, C2) in lane 0.
-template <typename T>
+// receives the second fluid's value.  Returns (C1, C2) in lane 0.  `stage` runs in every lane
+// right before the march (it places the node's far mask at `far_rows`, a work-group barrier).
+template <typename T, class Stage>
 __device__ __forceinline__ void fill_lanes(const FillNode &fn, const DomainDev &D, const uint8_t *flags,
-                                           const T *r, int line, bool active, double &c1, double &c2) {
+                                           const T *r, const uint32_t *far_rows, const Stage &stage, int line,
+                                           bool active, double &c1, double &c2) {
   const int64_t P = D.plane;
   auto fluid_at = [&](int i, int j) -> bool {
     const int dx = i - fn.i, dy = j - fn.j;
@@ -149,8 +151,9 @@ __device__ __forceinline__ void fill_lanes(const FillNode &fn, const DomainDev &
   const double nx = fn.nx, ny = fn.ny, tx = -ny, ty = nx;
   double v = 0.0;
   int ok = 0;
+  stage();
   if (active) {
-    const LineHit h = march_line_masked(fn.i, fn.j, cp * nx + sp * tx, cp * ny + sp * ty, fn.mask, fluid_at);
+    const LineHit h = march_line_masked(fn.i, fn.j, cp * nx + sp * tx, cp * ny + sp * ty, fn.mask, far_rows, fluid_at);
     if (h.ok) {
       const double ca = cfrac_at(r, P, node_q(h.i0, h.j0), k), cb = cfrac_at(r, P, node_q(h.i1, h.j1), k);
       v = ca + h.w * (cb - ca);

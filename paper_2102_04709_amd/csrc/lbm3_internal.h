@@ -199,14 +199,13 @@ __host__ __device__ inline LineHit march_line(int pi, int pj, double dx, double 
   return h;
 }
 
-// march_line with the fluid tests of the node's 11 x 11 block answered by its fluid mask: the same
-// crossings in the same order with the same arithmetic, as a loop without data-dependent
-// branches, so its hit is march_line's.  A line that needs a node outside the block (or more
-// crossings than the block can hold) before it hits is marched again by march_line, which reads
-// the flags there.
-template <class FluidAt>
-__host__ __device__ inline LineHit march_line_masked(int pi, int pj, double dx, double dy, const FluidMask &mask,
-                                                     const FluidAt &fluid) {
+// march_line with the fluid tests of a (2R + 1)^2 block around the node answered by test(dx, dy)
+// (a bit mask, no memory access): the same crossings in the same order with the same arithmetic,
+// so its hit is march_line's.  A line that needs a node outside the block (or more crossings than
+// the block can hold) before it hits is handed to fallback() from the start.
+template <int R, class BlockTest, class Fallback>
+__host__ __device__ inline LineHit march_line_block(int pi, int pj, double dx, double dy, const BlockTest &test,
+                                                    const Fallback &fallback) {
   LineHit h;
   h.ok = 0;
   h.i0 = h.j0 = h.i1 = h.j1 = 0;
@@ -216,7 +215,7 @@ __host__ __device__ inline LineHit march_line_masked(int pi, int pj, double dx, 
   const double ax = dx < 0 ? -dx : dx, ay = dy < 0 ? -dy : dy;
   const double iax = sx ? 1.0 / ax : 0.0, iay = sy ? 1.0 / ay : 0.0;
   int kx = 1, ky = 1;
-  for (int it = 0; it < 4 * kMaskR + 2; ++it) {
+  for (int it = 0; it < 4 * R + 2; ++it) {
     const double tx = sx ? (double)kx * iax : 1e300;  // t of the next vertical line
     const double ty = sy ? (double)ky * iay : 1e300;  // t of the next horizontal line
     const bool vert = tx <= ty;
@@ -236,16 +235,30 @@ __host__ __device__ inline LineHit march_line_masked(int pi, int pj, double dx, 
     // block offsets of the crossing's node (node) or of its two interpolation nodes
     const int a0 = vert ? line - pi : c0 - pi, b0 = vert ? c0 - pj : line - pj;
     const int a1 = (vert || node) ? a0 : a0 + 1, b1 = (vert && !node) ? b0 + 1 : b0;
-    if (a0 < -kMaskR || a1 > kMaskR || b0 < -kMaskR || b1 > kMaskR) break;
-    const bool f0 = mask.fluid(a0, b0), f1 = mask.fluid(a1, b1);
-    if (f0 && f1) {
+    if (a0 < -R || a1 > R || b0 < -R || b1 > R) break;
+    if (test(a0, b0) && test(a1, b1)) {
       h.ok = 1;
       h.i0 = pi + a0; h.j0 = pj + b0; h.i1 = pi + a1; h.j1 = pj + b1;
       h.w = node ? 0.0 : c - c0;
       return h;
     }
   }
-  return march_line(pi, pj, dx, dy, fluid);
+  return fallback();
+}
+
+// The wetting fill's march: the 11 x 11 mask of the fill record first; a line leaving it is
+// marched again over the 25 x 25 block of the node's far mask (rows of 25 bits, offsets -12..12,
+// bit dx + 12 of row dy + 12); beyond that march_line reads the flags.
+constexpr int kFarR = 12, kFarW = 2 * kFarR + 1;
+
+template <class FluidAt>
+__host__ __device__ inline LineHit march_line_masked(int pi, int pj, double dx, double dy, const FluidMask &mask,
+                                                     const uint32_t *far_rows, const FluidAt &fluid) {
+  auto near_test = [&](int a, int b) { return mask.fluid(a, b); };
+  auto far_test = [&](int a, int b) { return ((far_rows[b + kFarR] >> (a + kFarR)) & 1u) != 0; };
+  auto general = [&]() { return march_line(pi, pj, dx, dy, fluid); };
+  auto far = [&]() { return march_line_block<kFarR>(pi, pj, dx, dy, far_test, general); };
+  return march_line_block<kMaskR>(pi, pj, dx, dy, near_test, far);
 }
 
 // sin and cos of an angle in [0, pi/2] in FP64 (the wetting fill's line angle phi), to a few

@@ -15,6 +15,7 @@ struct FillArgs {
   int n_fill;
   const FillBlock *blocks;  // the work-groups' fill ranges
   int n_blocks;
+  const uint32_t *far;      // [kFarW * n_fill] far fluid masks of the fill nodes
   const DomainDev *doms;
   const uint8_t *flags;
   const T *rho;  // density planes of the current state

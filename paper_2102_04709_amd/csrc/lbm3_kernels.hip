@@ -32,14 +32,29 @@ namespace lbm3 {
 // slots of the state stay constant).
 template <typename T>
 __global__ __launch_bounds__(4 * kFillNodes) void wet_fill(FillArgs<T> A) {
+  __shared__ uint32_t far[kFillNodes][kFarW];  // the nodes' far fluid masks (for lines leaving the near one)
   const FillBlock B = A.blocks[blockIdx.x];
   const DomainDev &D = A.doms[B.dom];
   const int e = threadIdx.x >> 2, line = threadIdx.x & 3;
   const bool active = e < B.count;
   const int idx = B.first + (active ? e : 0);
   const FillNode fn = A.fill[idx];
+  // The far mask is loaded with the node and stored to LDS once the densities at D0 are in.
+  constexpr int kFarPerLane = (kFarW + 3) / 4;
+  uint32_t fr[kFarPerLane];
+#pragma unroll
+  for (int c = 0; c < kFarPerLane; ++c) {
+    const int k = line + 4 * c;
+    fr[c] = k < kFarW ? A.far[(size_t)idx * kFarW + k] : 0u;
+  }
+  auto stage = [&]() {
+#pragma unroll
+    for (int c = 0; c < kFarPerLane; ++c)
+      if (line + 4 * c < kFarW) far[e][line + 4 * c] = fr[c];
+    __syncthreads();
+  };
   double c1, c2;
-  fill_lanes<T>(fn, D, A.flags + D.base, A.rho + 3 * D.base, line, active, c1, c2);
+  fill_lanes<T>(fn, D, A.flags + D.base, A.rho + 3 * D.base, far[e], stage, line, active, c1, c2);
   if (active && line == 0) {
     A.fillC[3 * idx] = (T)c1;
     A.fillC[3 * idx + 1] = (T)c2;

@@ -1,5 +1,6 @@
 // Host check of two device helpers of the wetting fill (compiled for the CPU from the product
-// header): march_line_masked (11 x 11 mask block) must give exactly march_line's hit (same nodes, bit-identical weight)
+// header): march_line_masked (11 x 11 near mask, then the 25 x 25 far mask, then the general march)
+// must give exactly march_line's hit (same nodes, bit-identical weight)
 // for random fluid fields and directions, including lattice and rational-slope directions that
 // pass through nodes; sincos_quadrant must agree with long-double sin/cos to 1 ulp on the angle
 // range of Eq. (22)'s lines, [0, 85] degrees.
@@ -44,6 +45,12 @@ int main(int argc, char **argv) {
     for (int dy = -kMaskR; dy <= kMaskR; ++dy)
       for (int dx = -kMaskR; dx <= kMaskR; ++dx)
         if (field(pi + dx, pj + dy)) mask.set(dx, dy);
+    uint32_t far[kFarW];
+    for (int dy = -kFarR; dy <= kFarR; ++dy) {
+      far[dy + kFarR] = 0;
+      for (int dx = -kFarR; dx <= kFarR; ++dx)
+        if (field(pi + dx, pj + dy)) far[dy + kFarR] |= 1u << (dx + kFarR);
+    }
     auto fluid = [&](int i, int j) -> bool {  // as the fill's test: the mask inside the block
       const int dx = i - pi, dy = j - pj;
       if (FluidMask::inside(dx, dy)) return mask.fluid(dx, dy);
@@ -54,7 +61,7 @@ int main(int argc, char **argv) {
     if (trial % 7 == 1) ang = std::atan2((double)((int)(U(g) * 7) - 3), (double)((int)(U(g) * 7) - 3));
     const double dx = std::cos(ang), dy = std::sin(ang);
     const LineHit a = march_line(pi, pj, dx, dy, fluid);
-    const LineHit b = march_line_masked(pi, pj, dx, dy, mask, fluid);
+    const LineHit b = march_line_masked(pi, pj, dx, dy, mask, far, fluid);
     hits += a.ok;
     if (a.ok != b.ok || (a.ok && (a.i0 != b.i0 || a.j0 != b.j0 || a.i1 != b.i1 || a.j1 != b.j1 || a.w != b.w))) {
       if (++bad <= 5) std::printf("march mismatch, trial %ld angle %.17g\n", trial, ang);
