@@ -99,9 +99,10 @@ typedef struct {
                                 threads), 2 = row strips of 250 columns (256 threads), 3 = tiles
                                 with 512-thread work-groups; -1 = let lbm3_autotune choose
                                 (tiles until it runs) */
-  int32_t tile_x, tile_y;    /* tiles: the tile shape (0 = default; 256 threads: 32x8, 16x16,
-                                64x4, 64x8; 512 threads: 16x16, 32x16, 64x8); strips: tile_y =
-                                rows per segment (0 = default), tile_x unused */
+  int32_t tile_x, tile_y;    /* tiles: the tile shape (0 = default, the first listed; 256
+                                threads: 32x8, 16x16, 64x4, 64x8; 512 threads: 64x8, 16x16,
+                                32x16); strips: tile_y = rows per segment (0 = default), tile_x
+                                unused */
   int32_t persistent_blocks; /* > 0: the fused kernel runs this many work-groups that loop over
                                 the (domain, tile) work list; 0: one work-group per work item */
   int32_t adjoint;           /* 1: also lay out the scratch of the adjoint step (lbm3_adjoint_*);

@@ -23,9 +23,8 @@ enum {
                  //    outlet, whose node reads its neighbours'; elsewhere recomputed where needed)
   AL_F = 21,     // 2: adjoint of F (fluid nodes)
   AL_N = 23,     // 6: adjoint of n (fluid nodes)
-  AL_G = 29,     // 6: adjoint of the colour gradients
-  AL_C = 35,     // 4: adjoint of C_k and rho
-  A_PLANES = 39
+  AL_C = 29,     // 4: adjoint of C_k and rho
+  A_PLANES = 33
 };
 
 template <typename S, typename T>

@@ -532,6 +532,8 @@ __device__ __forceinline__ void pair_stress_vjp(const T cc[3], const T g[3][2], 
 // position z is read by the divergence F(y) = 3 sum_a w_a T(y + e_a) . e_a (Eq. 12 on Eq. 10)
 // of the fluid nodes y = z - e_a (periodic axes wrap, other axes do not), so the adjoint of the
 // stress at z is gathered from their adjoint forces; the normals at z matter only at fluid nodes.
+// The adjoint of the colour gradients at z then goes through the transpose of the Eq. (12)
+// stencil: an atomic scatter to the adjoint of C at the (clamped / wrapped) nodes z + e_a.
 template <typename S, typename T>
 __global__ __launch_bounds__(kThreads) void adj_stress(AdjArgs<S, T> A) {
   __shared__ T sC[3][kAdjN1];       // C_k at the nodes the ring-1 block's reads see
@@ -587,10 +589,7 @@ __global__ __launch_bounds__(kThreads) void adj_stress(AdjArgs<S, T> A) {
     for (int c = 0; c < 3; ++c) any |= lt[c] != T(0);
 #pragma unroll
     for (int c = 0; c < 6; ++c) any |= ln[c] != T(0);
-    if (!any) {
-#pragma unroll
-      for (int c = 0; c < 6; ++c) A.X[(AL_G + c) * AP + q] = T(0);
-    } else {
+    if (any) {
       int ci = i, cj = j;
       cmap(D, ci, cj);
       const int64_t qc = aidx(D, ci, cj);
@@ -611,47 +610,26 @@ __global__ __launch_bounds__(kThreads) void adj_stress(AdjArgs<S, T> A) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) aadd(&A.X[(AL_C + c) * AP + qc], lc[c]);
       aadd(&A.X[(AL_C + 3) * AP + qc], lrho);
+      bool anyg = false;
 #pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        A.X[(AL_G + 2 * k) * AP + q] = lg[k][0];
-        A.X[(AL_G + 2 * k + 1) * AP + q] = lg[k][1];
+      for (int k = 0; k < 3; ++k) anyg |= (lg[k][0] != T(0)) | (lg[k][1] != T(0));
+      if (anyg) {
+#pragma unroll
+        for (int a = 1; a < 9; ++a) {
+          const int ex = lat_ex(a), ey = lat_ey(a);
+          int ii = i + ex, jj = j + ey;
+          cmap(D, ii, jj);
+          const int64_t w = aidx(D, ii, jj);
+          const T c = T(3) * wgt<T>(a);
+#pragma unroll
+          for (int k = 0; k < 3; ++k) aadd(&A.X[(AL_C + k) * AP + w], c * (T(ex) * lg[k][0] + T(ey) * lg[k][1]));
+        }
       }
 #pragma unroll
       for (int c = 0; c < 3; ++c) sraw[c] = (double)lsig[c];
     }
   }
   block_add(sraw, A.raw + 9 * wk.dom);
-}
-
-// Adjoint of the colour-gradient stencil (Eq. 12).
-template <typename S, typename T>
-__global__ __launch_bounds__(kThreads) void adj_grad(AdjArgs<S, T> A) {
-  const int wi = adj_item(A.n_work);
-  if (wi < 0) return;
-  const WorkItem wk = A.work[wi];
-  const DomainDev &D = A.doms[wk.dom];
-  int i, j;
-  if (!tile_node(wk, i, j)) return;
-  const int64_t AP = A.aplane;
-  const int64_t q = aidx(D, i, j);
-  T lg[6];
-  bool any = false;
-#pragma unroll
-  for (int c = 0; c < 6; ++c) {
-    lg[c] = A.X[(AL_G + c) * AP + q];
-    any |= lg[c] != T(0);
-  }
-  if (!any) return;
-#pragma unroll
-  for (int a = 1; a < 9; ++a) {
-    const int ex = lat_ex(a), ey = lat_ey(a);
-    int ii = i + ex, jj = j + ey;
-    cmap(D, ii, jj);
-    const int64_t w = aidx(D, ii, jj);
-    const T c = T(3) * wgt<T>(a);
-#pragma unroll
-    for (int k = 0; k < 3; ++k) aadd(&A.X[(AL_C + k) * AP + w], c * (T(ex) * lg[2 * k] + T(ey) * lg[2 * k + 1]));
-  }
 }
 
 // Adjoint of C_k = rho_k / rho, rho = sum_k rho_k at fluid nodes.
@@ -857,7 +835,6 @@ hipError_t launch_adjoint(const AdjArgs<S, T> &a, int64_t tplane, hipStream_t s)
   const dim3 g((a.n_work + 7) / 8 * 8), b(kThreads);
   hipLaunchKernelGGL((adj_node<S, T>), g, b, 0, s, a, tplane);
   hipLaunchKernelGGL((adj_stress<S, T>), g, b, 0, s, a);
-  hipLaunchKernelGGL((adj_grad<S, T>), g, b, 0, s, a);
   hipLaunchKernelGGL((adj_comp<S, T>), g, b, 0, s, a, tplane);
   if (a.n_fill > 0)
     hipLaunchKernelGGL((adj_fill<S, T>), dim3((4 * a.n_fill + kThreads - 1) / kThreads), b, 0, s, a, tplane);

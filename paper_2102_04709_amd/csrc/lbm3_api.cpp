@@ -890,8 +890,8 @@ lbm3_status lbm3_create(const lbm3_domain *d, int32_t n, const lbm3_options *o, 
   c->graph_block = o->graph_block_steps > 0 ? round_up(o->graph_block_steps, 2) : 0;
   c->persistent = o->persistent_blocks;
   c->mode = o->kernel > 0 ? o->kernel : MODE_TILE;
-  if (is_tile_mode(c->mode)) {
-    c->tx = o->tile_x > 0 ? o->tile_x : 32;
+  if (is_tile_mode(c->mode)) {  // default shapes: 32x8 (256 threads), 64x8 (512 threads)
+    c->tx = o->tile_x > 0 ? o->tile_x : (c->mode == MODE_TILE512 ? 64 : 32);
     c->ty = o->tile_y > 0 ? o->tile_y : 8;
   } else {
     c->tx = 0;

@@ -184,12 +184,14 @@ __global__ __launch_bounds__(NT, sizeof(T) == 8 ? 1 : (sizeof(S) == 2 ? 5 : 6)) 
       // Eq. (13)-(15): the recolouring vectors of the fluid nodes of tile + 1 ring, from the
       // normals just formed (phase C needs only them, not the normals)
       if (!FIELDS && lx >= 1 && lx <= W2 - 2 && ly >= 1 && ly <= H2 - 2 && !(L.FL[p3] & FL_SOLID)) {
-        const int p1 = (lx - 1) + (ly - 1) * W1;
-        const T rt = L.RH[q];
-        T Rv[4];
-        recolour_R(cc[0] * rt, cc[1] * rt, cc[2] * rt, rt, nrm, K, Rv);
+        if (!ADJ) {  // (the adjoint's tiles do not stream)
+          const int p1 = (lx - 1) + (ly - 1) * W1;
+          const T rt = L.RH[q];
+          T Rv[4];
+          recolour_R(cc[0] * rt, cc[1] * rt, cc[2] * rt, rt, nrm, K, Rv);
 #pragma unroll
-        for (int c = 0; c < 4; ++c) L.PR[c * N1 + p1] = Rv[c];
+          for (int c = 0; c < 4; ++c) L.PR[c * N1 + p1] = Rv[c];
+        }
         if (ADJ) {  // pair normals of the tile's fluid nodes
           const int gx = x0 - 2 + lx, gy = y0 - 2 + ly;
           if (lx >= 2 && ly >= 2 && gx < wk.x1 && gy < wk.y1 && gx >= 0 && gx < D.nx && gy >= 0 && gy < D.ny) {
@@ -210,7 +212,7 @@ __global__ __launch_bounds__(NT, sizeof(T) == 8 ? 1 : (sizeof(S) == 2 ? 5 : 6)) 
       const int lx = q % W1, ly = q / W1;
       if (L.FL[(lx + 2) + (ly + 2) * W3] & FL_SOLID) return false;
       const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
-      if (FIELDS && !(lx >= 1 && lx <= TX && ly >= 1 && ly <= TY)) return false;
+      if ((FIELDS || ADJ) && !(lx >= 1 && lx <= TX && ly >= 1 && ly <= TY)) return false;
       // Zou-He ghost columns are never streaming sources; off-grid rows are flagged solid.
       if (D.bcx == BCX_ZOUHE && (gx < 0 || gx >= D.nx)) return false;
       if (FIELDS && (gx >= D.nx || gy >= D.ny)) return false;
@@ -244,6 +246,14 @@ __global__ __launch_bounds__(NT, sizeof(T) == 8 ? 1 : (sizeof(S) == 2 ? 5 : 6)) 
       const int p3 = (lx + 2) + (ly + 2) * W3;
       const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
       T Fx = Fxs[it], Fy = Fys[it];
+      const bool zh_out = D.bcx == BCX_ZOUHE && gx >= D.nx - 2;
+      if (ADJ) {  // interfacial force of the tile's fluid nodes
+        if (!(gx < wk.x1 && gy < wk.y1 && gy >= 0 && gy < D.ny)) continue;
+        const int64_t a = adj_index(D, gx, gy);
+        A.adj_X[AX_F * A.adj_plane + a] = Fx;
+        A.adj_X[(AX_F + 1) * A.adj_plane + a] = Fy;
+        if (!zh_out) continue;  // the collision below only where a Zou-He outlet node reads it
+      }
       T f[9];
       {
         const int64_t li = inner ? plane_index(gx, gy, D.pitch) : node_index(gx, gy, D);
@@ -261,18 +271,11 @@ __global__ __launch_bounds__(NT, sizeof(T) == 8 ? 1 : (sizeof(S) == 2 ? 5 : 6)) 
         if (A.out_force) { A.out_force[o] = Fx; A.out_force[n + o] = Fy; }
         continue;
       }
-      if (ADJ) {  // interfacial force of the tile's fluid nodes; the post-collision populations
-                  // only in the two columns a Zou-He outlet node reads them from (the adjoint's
-                  // node kernel recomputes its own)
-        if (lx >= 1 && ly >= 1 && gx < wk.x1 && gy < wk.y1 && gy >= 0 && gy < D.ny) {
-          const int64_t a = adj_index(D, gx, gy);
-          A.adj_X[AX_F * A.adj_plane + a] = Fxs[it];
-          A.adj_X[(AX_F + 1) * A.adj_plane + a] = Fys[it];
-          if (D.bcx == BCX_ZOUHE && gx >= D.nx - 2) {
+      if (ADJ) {  // the post-collision populations in the two columns a Zou-He outlet node
+                  // reads them from (the adjoint's node kernel recomputes its own elsewhere)
+        const int64_t a = adj_index(D, gx, gy);
 #pragma unroll
-            for (int c = 0; c < 9; ++c) A.adj_X[(AX_P + c) * A.adj_plane + a] = fd[c];
-          }
-        }
+        for (int c = 0; c < 9; ++c) A.adj_X[(AX_P + c) * A.adj_plane + a] = fd[c];
         continue;
       }
 #pragma unroll

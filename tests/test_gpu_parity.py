@@ -159,7 +159,7 @@ def test_execution_variants_are_bitwise_identical(precision):
     families = {
         "tile": [dict(), dict(tile=(32, 8)), dict(tile=(16, 16)), dict(kernel="tile512", tile=(32, 16)),
                  dict(kernel="tile512", tile=(16, 16), graph_block_steps=10), dict(persistent_blocks=7),
-                 dict(graph_block_steps=8)],
+                 dict(graph_block_steps=8), dict(kernel="tile512")],
         "strip": [dict(kernel="strip128", tile=(0, 16)), dict(kernel="strip256", tile=(0, 40)),
                   dict(kernel="strip128", tile=(0, 8), persistent_blocks=5),
                   dict(kernel="strip256", tile=(0, 64), graph_block_steps=10)],
