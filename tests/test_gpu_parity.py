@@ -33,6 +33,8 @@ def _case(name):
         return W.capillary_intrusion(nx=200, ny=30, slug=40, lg=40, ratio=10.0)
     if name == "pillars_small":
         return W.pillar_domain(77, nx=200, ny=96, n_pillars=4)
+    if name == "pillars_tilted":  # lines 30 and 60 degrees off the normal: long marches round pillars
+        return W.pillar_domain(78, nx=200, ny=96, n_pillars=6, theta=(30.0, 120.0), sigma=(0.02, 0.01, 0.01))
     if name == "random_periodic":
         return W.random_mixture(97, 45, seed=5, walls=False)
     if name == "random_walls_circles":
@@ -44,7 +46,7 @@ def _case(name):
 
 
 CASES = ["flat_janus_theta12_0", "flat_janus_table1d", "cylinder_small", "capillary_small",
-         "pillars_small", "random_periodic", "random_walls_circles", "random_zouhe"]
+         "pillars_small", "pillars_tilted", "random_periodic", "random_walls_circles", "random_zouhe"]
 
 
 def _run_pair(lbm3, w, steps, precision="f64", **kw):
