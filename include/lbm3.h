@@ -161,7 +161,8 @@ lbm3_status lbm3_set_params(lbm3_ctx *c, int32_t domain, const double *theta_deg
  * as implemented (Eq. 1-22; at the non-smooth points -- the max/min of Eq. 22, clamps, the
  * |G| threshold of the normals -- the branch the forward took).  Needs a context created with
  * options.adjoint = 1.  lambda buffers are device buffers of lbm3_state_bytes in the state
- * layout and compute type; entries at solid nodes are zero.
+ * layout and compute type; entries at solid nodes are zero, and lbm3_adjoint_step leaves the
+ * layout's padding (plane columns beyond nx, off-grid rows of a periodic y axis) unwritten.
  *
  * lbm3_adjoint_seed starts a backward pass: clears the parameter-gradient accumulators and
  * writes lambda_T = dL/drho_k into dev_lambda (distribution part zero).  dev_grad_rho: device,

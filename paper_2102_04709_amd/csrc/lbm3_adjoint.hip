@@ -435,9 +435,12 @@ __global__ __launch_bounds__(kThreads) void adj_node(AdjArgs<S, T> A, int64_t tp
   __syncthreads();
   if (tile_node(wk, i, j) && i >= 0 && i < D.nx) {
     const int64_t q = aidx(D, i, j);
-    if (!fluid_node(A.flags, D, i, j)) {
+    if (!fluid_node(A.flags, D, i, j)) {  // (the output's distributions are zero at solid positions)
 #pragma unroll
       for (int c = 0; c < 4; ++c) A.X[(AL_C + c) * AP + q] = T(0);
+      const int64_t li = plane_index(i, j, D.pitch);
+#pragma unroll
+      for (int a = 0; a < 9; ++a) A.lout[9 * D.base + a * D.plane + li] = T(0);
     } else {
       const int64_t li = plane_index(i, j, D.pitch);
       const KT<T> K = make_kt<T>(D);
@@ -640,10 +643,15 @@ __global__ __launch_bounds__(kThreads) void adj_comp(AdjArgs<S, T> A, int64_t tp
   const WorkItem wk = A.work[wi];
   const DomainDev &D = A.doms[wk.dom];
   int i, j;
-  if (!tile_node(wk, i, j) || !fluid_node(A.flags, D, i, j)) return;
+  if (!tile_node(wk, i, j) || i < 0 || i >= D.nx) return;
+  const int64_t li = plane_index(i, j, D.pitch);
+  if (!fluid_node(A.flags, D, i, j)) {  // zero at solid positions (nothing else writes them)
+    T *o = A.lout + 9 * tplane + 3 * D.base + li;
+    o[0] = o[D.plane] = o[2 * D.plane] = T(0);
+    return;
+  }
   const int64_t AP = A.aplane;
   const int64_t q = aidx(D, i, j);
-  const int64_t li = plane_index(i, j, D.pitch);
   const T C0 = A.X[AX_C * AP + q], C1 = A.X[(AX_C + 1) * AP + q], C2 = A.X[(AX_C + 2) * AP + q];
   const T rt = A.X[(AX_C + 3) * AP + q];
   const T l0 = A.X[AL_C * AP + q], l1 = A.X[(AL_C + 1) * AP + q], l2 = A.X[(AL_C + 2) * AP + q];

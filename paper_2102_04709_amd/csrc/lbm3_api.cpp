@@ -766,9 +766,6 @@ lbm3_status fields_t(lbm3_ctx *c, int dom, void *rho, void *u, void *force) {
 
 template <typename S, typename T>
 lbm3_status adjoint_step_t(lbm3_ctx *c, const void *state, const void *lin, void *lout) {
-  size_t bytes = 0;
-  (void)lbm3_state_bytes(c, &bytes);
-  HIPC(c, hipMemsetAsync(lout, 0, bytes, c->stream));
   const size_t fb = 9 * (size_t)c->L.total_plane * sizeof(S);
   const S *fin = reinterpret_cast<const S *>(state);
   const T *rin = reinterpret_cast<const T *>(reinterpret_cast<const char *>(state) + fb);

@@ -153,14 +153,14 @@ def test_adjoint_batched_domains_vs_oracle_fd():
         assert err.max() <= 1e-5
 
 
-def _fluid_state_mask(w, precision_bytes=8):
-    """Mask of the state entries (12 planes: 9 distributions, 3 densities) at fluid nodes, in
-    the state layout of a single domain: planes of pitch * (ny + 4) elements, pitch = nx
-    rounded up to 64, node (i, j) at i + pitch * (j + 2)."""
+def _fluid_state_mask(w, precision_bytes=8, solid=False):
+    """Mask of the state entries (12 planes: 9 distributions, 3 densities) at fluid nodes (at
+    solid nodes with solid=True), in the state layout of a single domain: planes of
+    pitch * (ny + 4) elements, pitch = nx rounded up to 64, node (i, j) at i + pitch * (j + 2)."""
     pitch = (w.nx + 63) // 64 * 64
     P = pitch * (w.ny + 4)
     m = np.zeros((12, P), bool)
-    jj, ii = np.nonzero(w.solid == 0)
+    jj, ii = np.nonzero((w.solid != 0) if solid else (w.solid == 0))
     li = ii + pitch * (jj + 2)
     m[:, li] = True
     return m.reshape(-1)
@@ -192,14 +192,17 @@ def test_adjoint_of_state_directional():
     C = rollout.phase_fields(rho, [w])[0]
     (((C - tgt) ** 2) * fl).sum().backward()
     lam = torch.empty_like(s0)
-    lam2 = torch.empty_like(s0)
+    lam2 = torch.full_like(s0, 255)  # NaN everywhere: every node entry must be written
     sim.adjoint_seed(rho.grad, lam)
     for t in reversed(range(steps)):
         sim.adjoint_step(states[t], lam, lam2)
         lam, lam2 = lam2, lam
     lam0 = lam.view(torch.float64)
     mask = torch.as_tensor(_fluid_state_mask(w), device=s0.device)
-    assert float((lam0 * (~mask)).abs().max()) == 0.0  # entries at solid nodes stay zero
+    smask = torch.as_tensor(_fluid_state_mask(w, solid=True), device=s0.device)
+    for buf in (lam0, lam2.view(torch.float64)):  # lambda_0, and lambda_1 in the buffer that began as NaN
+        assert bool(torch.isfinite(buf[mask | smask]).all())
+        assert float(buf[smask].abs().max()) == 0.0  # entries at solid nodes are zero
     n9 = 9 * (lam0.numel() // 12)
     gen = torch.Generator(device="cpu").manual_seed(5)
     for part, sl in (("distributions", slice(0, n9)), ("densities", slice(n9, None))):
@@ -213,7 +216,7 @@ def test_adjoint_of_state_directional():
         sp = (s0.view(torch.float64) + eps * delta).contiguous().view(torch.uint8)
         sm = (s0.view(torch.float64) - eps * delta).contiguous().view(torch.uint8)
         fd = (loss_from(sp) - loss_from(sm)) / (2 * eps)
-        ad = float((lam0 * delta).sum())
+        ad = float((lam0[mask] * delta[mask]).sum())
         print(f"directional ({part}): adjoint {ad:.12e} fd {fd:.12e}", flush=True)
         assert abs(ad - fd) <= 1e-6 * abs(fd)
     sim.close()
