@@ -74,3 +74,23 @@ def test_bad_options_rejected(lib):
     w = W.flat_janus()
     with pytest.raises(lbm3.Lbm3Error):
         _bytes([w], precision=7)
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """No fallback: without the built HIP library the binding raises instead of computing."""
+    monkeypatch.setattr(lbm3, "LIB_PATH", str(tmp_path / "liblbm3.so"))
+    monkeypatch.setattr(lbm3, "_lib", None)
+    with pytest.raises(RuntimeError, match="not built"):
+        lbm3.library()
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py runs on one GPU; --gpus 2 exits with status 2 and says so."""
+    import json
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120, cwd=ROOT)
+    assert r.returncode == 2
+    msg = json.loads(r.stdout.strip().splitlines()[-1])
+    assert "one GPU" in msg["error"]
