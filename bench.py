@@ -93,7 +93,7 @@ def measure(workloads_, precision, steps, warmup, graph=100, config=None):
     from paper_2102_04709_amd import lbm3
     if config is None:
         sim = lbm3.Simulation(workloads_, precision=precision, graph_block_steps=graph)
-        tile = sim.autotune(3)
+        tile = sim.autotune(20)  # 20 launches per candidate: a stable pick between close configurations
     else:
         k, tx, ty = config
         sim = lbm3.Simulation(workloads_, precision=precision, graph_block_steps=graph, kernel=int(k),
