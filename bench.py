@@ -7,8 +7,8 @@ nodes.  The same JSON line carries the FP64 and FP16-storage variants, the x10 s
 workload (4000 x 4000, 1.5 GB of FP32 state, so HBM rather than the 256 MB Infinity Cache sets
 the bound), the 96-domain batched pillar sweep in one launch per step, the roofline of the fused
 kernel from HIP events on its own stream, the adjoint step and the checkpointed forward +
-backward rollout on the 512 x 256 inverse problem (FP32 and FP64), and the FP64 CPU oracle
-timed on a bounded sample.
+backward rollout on the 512 x 256 inverse problem (FP32 and FP64), the FP32 adjoint step on the
+4000 x 4000 workload, and the FP64 CPU oracle timed on a bounded sample (about 10-20 s).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--skip-extra] [--skip-cpu]
 """
