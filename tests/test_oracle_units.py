@@ -303,3 +303,86 @@ def test_inconsistent_angles_rejected():
     w = W.flat_janus(nx=30, ny=12, R=4, theta=(40.0, 110.0), sigma=(0.01, 0.01, 0.01))
     with pytest.raises(ValueError, match="Eq. \\(18\\)"):
         po.Oracle(w)
+
+
+def _brute_force_march(solid, y_periodic, pi, pj, dx, dy, t_max=24.0, eps=1e-9):
+    """The characteristic-line crossing of the wetting fill written straight from its reading:
+    every crossing of the ray (pi, pj) + t (dx, dy), 0 < t <= t_max, with a grid line x = integer
+    or y = integer, in increasing t; a crossing within eps of a node is that node, otherwise the
+    two nodes of the crossed grid line bracket it; the first crossing whose nodes are all fluid is
+    the hit.  Periodic x; y periodic or solid outside the grid.  Returns (ok, n0, n1, w) with the
+    nodes mapped into the grid (rows outside a non-periodic y axis clamped to -2 .. ny + 1)."""
+    ny, nx = solid.shape
+
+    def mapped(i, j):
+        i %= nx
+        j = j % ny if y_periodic else min(max(j, -2), ny + 1)
+        return i, j
+
+    def fluid(i, j):
+        i, j = mapped(i, j)
+        return 0 <= j < ny and solid[j, i] == 0
+
+    cands = []  # (t, kind, line index)
+    for d, p, kind in ((dx, pi, "v"), (dy, pj, "h")):
+        if abs(d) < 1e-12:
+            continue
+        s = 1 if d > 0 else -1
+        k = p + s
+        while True:
+            t = (k - p) / d
+            if t > t_max:
+                break
+            cands.append((t, kind, k))
+            k += s
+    cands.sort()
+    seen_nodes = set()
+    for t, kind, k in cands:
+        if kind == "v":
+            x, y = float(k), pj + t * dy
+        else:
+            x, y = pi + t * dx, float(k)
+        xr, yr = round(x), round(y)
+        if abs(x - xr) < eps and abs(y - yr) < eps:
+            node = (int(xr), int(yr))
+            if node in seen_nodes:
+                continue
+            seen_nodes.add(node)
+            if fluid(*node):
+                return True, mapped(*node), mapped(*node), 0.0
+            continue
+        if kind == "v":
+            j0 = int(np.floor(y))
+            a, b, w = (int(k), j0), (int(k), j0 + 1), y - j0
+        else:
+            i0 = int(np.floor(x))
+            a, b, w = (i0, int(k)), (i0 + 1, int(k)), x - i0
+        if fluid(*a) and fluid(*b):
+            return True, mapped(*a), mapped(*b), w
+    return False, None, None, 0.0
+
+
+@pytest.mark.parametrize("seed, walls", [(3, True), (4, False), (5, True)])
+def test_march_matches_brute_force_crossings(seed, walls):
+    """The oracle's characteristic-line march (Eq. 22's crossing D) against the brute-force
+    enumeration of all grid-line crossings, from every fill node, along random directions and
+    along lattice directions that pass exactly through nodes."""
+    w = W.random_mixture(48, 36, seed, walls=walls, circles=[(17.3, 16.6, 6.1), (34.2, 20.7, 4.4)])
+    o = po.Oracle(w)
+    idx, _ = o.fill_nodes()
+    rng = np.random.Generator(np.random.PCG64(seed))
+    lattice = [(1, 0), (0, 1), (-1, 0), (0, -1), (1, 1), (-1, 1), (1, -1), (-1, -1), (2, 1), (1, -2), (-3, 1)]
+    checked = hits = 0
+    for n, (i, j) in enumerate(idx[:, :2]):
+        dirs = [(np.cos(a), np.sin(a)) for a in rng.uniform(0, 2 * np.pi, 6)]
+        dirs += [(a / np.hypot(a, b), b / np.hypot(a, b)) for a, b in lattice[n % 3::3]]
+        for dx, dy in dirs:
+            ok, n0, n1, wt = o.march(int(i), int(j), float(dx), float(dy))
+            bok, b0, b1, bw = _brute_force_march(w.solid, w.y_periodic, int(i), int(j), dx, dy)
+            assert ok == bok, (i, j, dx, dy)
+            if ok:
+                hits += 1
+                assert (n0, n1) == (b0, b1), (i, j, dx, dy, n0, n1, b0, b1)
+                assert abs(wt - bw) <= 1e-12, (wt, bw)
+            checked += 1
+    assert checked > 500 and hits > checked // 4  # (directions into the solid may find no fluid)
