@@ -17,10 +17,13 @@
 //   Sec. III                 flow boundary conditions: halfway bounce-back (III A), modified
 //                            periodic exchange of fluids 1 and 3 (III C), Zou-He velocity inlet
 //                            and pressure outlet (III D)
-// Where the paper is silent the readings implemented here are the ones listed under "Readings"
-// in the design notes of the repository; each is marked "reading:" below.
+// Where the paper is silent or ambiguous, the choice made is marked "reading:" below.
 // Parity status: every stage is pinned by a CPU test (tests/test_oracle_*.py) against closed
-// forms, invariants or physics; see the pin list in the design notes.
+// forms, invariants, brute force (the characteristic-line march) or physics.  Parity unpinned:
+// the numerical constants of the readings -- the |G| threshold of the normals, C taken at D0 for
+// Eq. (21), the 1e-9 node tolerance, the t = 24 end and the fallbacks of the line march, and the
+// 5/175 degree clamp of the line angle -- which the physics pins constrain only through the
+// contact angles they produce.
 
 #include <algorithm>
 #include <cmath>
