@@ -202,7 +202,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
-                                   "(multi-GPU sharding is a design note, not implemented)"}))
+                                   "(sharding across GPUs is not implemented)"}))
         sys.exit(2)
     import torch
     from paper_2102_04709_amd import workloads as W
