@@ -201,7 +201,7 @@ def main():
                     help="also run a 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+        print(json.dumps({"error": "bench.py runs on one GPU only; --gpus must be 1 "
                                    "(sharding across GPUs is not implemented)"}))
         sys.exit(2)
     import torch
