@@ -134,6 +134,45 @@ def test_fp64_full_size_capillary_and_pillar_configs():
         assert np.abs(g["rho"] - o.rho())[:, fluid].max() <= 1e-10, w.name
 
 
+def test_full_size_batched_sweep_sampled_against_oracle():
+    """The 96-domain pillar sweep at full size (19.7 M nodes) in the launch form the benchmark
+    times (one batched launch per step over all domains, 512-thread 32 x 16 tiles, hipGraph
+    blocks): in FP64, sampled domains (the largest, and domains at 30 and 150 degrees) match their
+    individual oracles after 20 steps; FP32 matches the FP64 run on every domain."""
+    lbm3 = _lbm3()
+    ws = W.pillar_sweep()
+    steps = 20
+    runs = {}
+    for prec in ("f64", "f32"):
+        sim = lbm3.Simulation(ws, precision=prec, kernel="tile512", tile=(32, 16), graph_block_steps=10)
+        sim.step(steps)
+        runs[prec] = sim
+    sizes = [w.nx * w.ny for w in ws]
+    pick = {int(np.argmax(sizes))}
+    for ang in (30.0, 150.0):
+        cands = [d for d, w in enumerate(ws) if w.theta_deg[0] == ang]
+        if cands:
+            pick.add(max(cands, key=lambda d: sizes[d]))
+    po.set_threads(po.max_threads())
+    for d in sorted(pick):
+        w = ws[d]
+        print(f"sweep domain {d}: {w.nx}x{w.ny}, theta {w.theta_deg}", flush=True)
+        o = po.Oracle(w)
+        o.step(steps)
+        r = runs["f64"].fields(d, velocity=False, force=False)["rho"].cpu().numpy()
+        fluid = w.solid == 0
+        assert np.abs(r - o.rho())[:, fluid].max() <= 1e-10, d
+    worst = 0.0
+    for d, w in enumerate(ws):
+        a = runs["f64"].fields(d, velocity=False, force=False)["rho"].cpu().numpy()
+        b = runs["f32"].fields(d, velocity=False, force=False)["rho"].double().cpu().numpy()
+        worst = max(worst, float(np.abs(a - b)[:, w.solid == 0].max()))
+    print(f"sweep FP32 vs FP64 after {steps} steps: {worst:.2e}", flush=True)
+    assert worst <= 1e-5
+    for sim in runs.values():
+        sim.close()
+
+
 def test_batched_domains_match_individual_oracles():
     lbm3 = _lbm3()
     ws = [_case("flat_janus_table1d"), _case("pillars_small"), _case("random_walls_circles")]
