@@ -21,9 +21,8 @@
 // Parity status: every stage is pinned by a CPU test (tests/test_oracle_*.py) against closed
 // forms, invariants, brute force (the characteristic-line march) or physics.  Parity unpinned:
 // the numerical constants of the readings -- the |G| threshold of the normals, C taken at D0 for
-// Eq. (21), the 1e-9 node tolerance, the t = 24 end and the fallbacks of the line march, and the
-// 5/175 degree clamp of the line angle -- which the physics pins constrain only through the
-// contact angles they produce.
+// Eq. (21), the 1e-9 node tolerance, the t = 24 end and the fallbacks of the line march -- which
+// the physics pins constrain only through the contact angles they produce.
 
 #include <algorithm>
 #include <cmath>

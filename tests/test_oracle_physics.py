@@ -261,7 +261,7 @@ def test_flat_interfaces_at_90_degrees_relax_straight_and_at_rest():
 
 
 def _fill_case(C1, C2, theta):
-    nx, ny = 40, 12
+    nx, ny = len(C1), 12
     solid = W._walls(nx, ny)
     rho = np.zeros((3, ny, nx))
     rho[0] = C1[None, :]
@@ -297,6 +297,27 @@ def test_fill_closed_form_flat_wall(theta13):
         top = o.ny - 1
         expect = C1[i] + (1 if theta13 <= 90 else -1) * abs(b) * math.tan(phi)
         assert abs(Cext[0, top + PY, i] - expect) < 1e-13
+
+
+@pytest.mark.parametrize("theta13, clamped", [(2.0, 5.0), (178.0, 175.0), (5.0, 5.0)])
+def test_fill_line_angle_clamped(theta13, clamped):
+    """The line-angle clamp (reading: theta_k within [5, 175] degrees for the line construction):
+    at 2 degrees the lines leave at |90 - 5| = 85 degrees from the normal, so they meet row 1 at
+    x = i +- tan(85) and row 1 from the second layer at i +- 2 tan(85) (line lengths 11.5 and 22.9,
+    inside t = 24); unclamped, 88 degrees would put the second-layer crossing beyond t = 24."""
+    nx = 200
+    x = np.arange(nx, dtype=float)
+    b = 0.002
+    C1 = 0.3 + b * (x - nx / 2)
+    C2 = np.zeros(nx)
+    o, Cext = _fill_case(C1, C2, (theta13, 90.0))
+    PY = o.PY
+    t = math.tan(math.radians(abs(90 - clamped)))
+    for i in range(60, 140):
+        for depth, row in ((1, 0), (2, -1)):
+            expect = C1[i] + (1 if clamped <= 90 else -1) * depth * b * t
+            got = Cext[0, row + PY, i]
+            assert abs(got - expect) < 1e-12, (theta13, i, row, got, expect)
 
 
 def test_fill_uses_pair_angle_between_fluids_1_and_2():
