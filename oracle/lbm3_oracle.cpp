@@ -20,9 +20,9 @@
 // Where the paper is silent or ambiguous, the choice made is marked "reading:" below.
 // Parity status: every stage is pinned by a CPU test (tests/test_oracle_*.py) against closed
 // forms, invariants, brute force (the characteristic-line march) or physics.  Parity unpinned:
-// the numerical constants of the readings -- the |G| threshold of the normals, C taken at D0 for
-// Eq. (21), the 1e-9 node tolerance, the t = 24 end and the fallbacks of the line march -- which
-// the physics pins constrain only through the contact angles they produce.
+// the numerical constants of the readings -- the |G| threshold of the normals, the 1e-9 node
+// tolerance, the t = 24 end and the fallbacks of the line march -- which the physics pins
+// constrain only through the contact angles they produce.
 
 #include <algorithm>
 #include <cmath>

@@ -320,6 +320,36 @@ def test_fill_line_angle_clamped(theta13, clamped):
             assert abs(got - expect) < 1e-12, (theta13, i, row, got, expect)
 
 
+def test_fill_weighted_angle_from_C_at_D0():
+    """Eq. (21) with all three fluids at a flat wall: theta_1 = (C3 theta13 + C2 theta12) /
+    (C2 + C3) and theta_2 = (C3 theta23 + C1 theta21) / (C1 + C3), theta21 = 180 - theta12, with
+    the C's taken at D0 (reading: the first crossing of the normal line, here the node above P);
+    each fluid's lines then meet row 1 at x = i +- tan|90 - theta_k| and Eq. (22) keeps the larger
+    value for theta_k <= 90, the smaller above."""
+    nx = 120
+    x = np.arange(nx, dtype=float)
+    C1 = 0.25 + 0.002 * (x - nx / 2)
+    C2 = 0.35 - 0.0015 * (x - nx / 2)
+    theta = (60.0, 100.0)
+    o, Cext = _fill_case(C1, C2, theta)
+    PY = o.PY
+    t12 = math.degrees(o.theta12())
+    C3 = 1 - C1 - C2
+    for i in range(30, 90):
+        for k, (Ck, th_a, th_b, wa, wb) in enumerate(((C1, theta[0], t12, C2[i], C3[i]),
+                                                      (C2, theta[1], 180 - t12, C1[i], C3[i]))):
+            th = (wb * th_a + wa * th_b) / (wa + wb)
+            phi = math.radians(abs(90 - th))
+            vals = []
+            for sgn in (1, -1):
+                xc = i + sgn * math.tan(phi)
+                i0 = int(math.floor(xc))
+                vals.append(Ck[i0] + (xc - i0) * (Ck[i0 + 1] - Ck[i0]))
+            expect = max(vals) if th <= 90 else min(vals)
+            got = Cext[k, PY, i]
+            assert abs(got - expect) < 1e-12, (k, i, got, expect)
+
+
 def test_fill_uses_pair_angle_between_fluids_1_and_2():
     """With fluid 3 absent, Eq. (21) reduces to theta_1 = theta12 and theta_2 = 180 - theta12."""
     x = np.arange(40, dtype=float)
