@@ -192,7 +192,10 @@ bool validate_and_build(const lbm3_domain &d, int dom, double beta0, DomHost &H,
   D.plane = (int64_t)pitch * rows;
   D.u_in = d.u_in;
   D.rho_out = d.rho_out;
-  for (int k = 0; k < 3; ++k) D.nu[k] = d.nu[k];
+  for (int k = 0; k < 3; ++k) {
+    D.nu[k] = d.nu[k];
+    D.inu[k] = 1.0 / d.nu[k];
+  }
   (void)derive_params(d.theta_deg, d.sigma, D);
   D.beta0 = beta0;
   D.g[0] = d.body_force[0];

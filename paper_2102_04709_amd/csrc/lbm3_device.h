@@ -212,7 +212,7 @@ __device__ __forceinline__ KT<T> make_kt(const DomainDev &D) {
   KT<T> K;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    K.inu[k] = (T)(1.0 / D.nu[k]);
+    K.inu[k] = (T)D.inu[k];
     K.sig[k] = (T)D.sig[k];
     K.gX[k] = (T)D.gX[k];
   }

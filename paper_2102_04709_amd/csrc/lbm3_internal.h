@@ -50,6 +50,7 @@ struct DomainDev {
   int64_t goff;   // element offset of this domain in flat [3][ny][nx] field arrays
   double u_in, rho_out;
   double nu[3];
+  double inu[3];   // 1 / nu_k, formed on the host (IEEE FP64 division)
   double sig[3];   // sigma12, sigma13, sigma23
   double gX[3];    // g(X_kl) of Eq. (15) for the pairs 12, 13, 23
   double beta0;
