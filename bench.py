@@ -29,21 +29,21 @@ HBM_PEAK_GBS = 8000.0
 # precision and kernel configuration, valid for the kernel sources with the given digest only.
 KERNEL_SOURCES = ("lbm3_kernels.hip", "lbm3_device.h", "lbm3_internal.h", "lbm3_kernels.h", "lbm3_adjoint.h")
 TRAFFIC = {
-    "digest": "6dd0a3551dbb5d14",
-    ('cylinder_janus', 400, 'f32', (0, 16, 16)): (4490.5 * 2.0 + 6969.0 * 1.0) * 1024,
-    ('cylinder_janus', 400, 'f32', (3, 16, 16)): (4872.2 * 2.0 + 8219.0 * 1.0) * 1024,
-    ('cylinder_janus', 400, 'f32', (0, 32, 8)): (4368.8 * 2.0 + 6969.0 * 1.0) * 1024,
-    ('cylinder_janus', 400, 'f32', (3, 32, 16)): (4484.3 * 2.0 + 6969.0 * 1.0) * 1024,
-    ('cylinder_janus', 400, 'f32', (3, 64, 8)): (4358.1 * 2.0 + 6969.0 * 1.0) * 1024,
-    ('cylinder_janus', 400, 'f32', (0, 64, 4)): (4290.8 * 2.0 + 6969.0 * 1.0) * 1024,
-    ('cylinder_janus', 400, 'f32', (0, 64, 8)): (6476.9 * 2.0 + 12219.0 * 1.0) * 1024,
-    ('cylinder_janus', 400, 'f32', (1, 0, 32)): (4649.1 * 2.0 + 7543.4 * 1.0) * 1024,
-    ('cylinder_janus', 400, 'f32', (2, 0, 32)): (4133.6 * 2.0 + 7471.0 * 1.0) * 1024,
-    ('cylinder_janus', 400, 'f32', (2, 0, 64)): (4133.6 * 2.0 + 7369.2 * 1.0) * 1024,
-    ('cylinder_janus_x10', 4000, 'f32', (0, 32, 8)): (363842.6 * 2.0 + 696999.2 * 1.0) * 1024,
-    ('cylinder_janus_x10', 4000, 'f32', (0, 16, 16)): (429336.2 * 2.0 + 699735.1 * 1.0) * 1024,
-    ('cylinder_janus_x10', 4000, 'f32', (3, 64, 8)): (362889.4 * 2.0 + 696999.2 * 1.0) * 1024,
-    ('cylinder_janus_x10', 4000, 'f32', (3, 32, 16)): (372423.7 * 2.0 + 696999.7 * 1.0) * 1024,
+    "digest": "84f060436a832b72",
+    ('cylinder_janus', 400, 'f32', (0, 16, 16)): (4493.6 * 2.0 + 6969.0 * 1.0) * 1024,
+    ('cylinder_janus', 400, 'f32', (3, 16, 16)): (4873.6 * 2.0 + 8219.0 * 1.0) * 1024,
+    ('cylinder_janus', 400, 'f32', (0, 32, 8)): (4367.9 * 2.0 + 6969.0 * 1.0) * 1024,
+    ('cylinder_janus', 400, 'f32', (3, 32, 16)): (4482.3 * 2.0 + 6969.0 * 1.0) * 1024,
+    ('cylinder_janus', 400, 'f32', (3, 64, 8)): (4360.6 * 2.0 + 6969.0 * 1.0) * 1024,
+    ('cylinder_janus', 400, 'f32', (0, 64, 4)): (4293.2 * 2.0 + 6969.0 * 1.0) * 1024,
+    ('cylinder_janus', 400, 'f32', (0, 64, 8)): (6474.0 * 2.0 + 12219.0 * 1.0) * 1024,
+    ('cylinder_janus', 400, 'f32', (1, 0, 32)): (4646.9 * 2.0 + 7554.2 * 1.0) * 1024,
+    ('cylinder_janus', 400, 'f32', (2, 0, 32)): (4132.0 * 2.0 + 7424.2 * 1.0) * 1024,
+    ('cylinder_janus', 400, 'f32', (2, 0, 64)): (4132.0 * 2.0 + 7327.5 * 1.0) * 1024,
+    ('cylinder_janus_x10', 4000, 'f32', (0, 32, 8)): (363930.7 * 2.0 + 696999.4 * 1.0) * 1024,
+    ('cylinder_janus_x10', 4000, 'f32', (0, 16, 16)): (428324.9 * 2.0 + 700333.1 * 1.0) * 1024,
+    ('cylinder_janus_x10', 4000, 'f32', (3, 64, 8)): (362953.6 * 2.0 + 696999.2 * 1.0) * 1024,
+    ('cylinder_janus_x10', 4000, 'f32', (3, 32, 16)): (372891.2 * 2.0 + 696999.5 * 1.0) * 1024,
 }
 
 

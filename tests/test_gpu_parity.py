@@ -188,6 +188,55 @@ def test_batched_domains_match_individual_oracles():
         np.testing.assert_allclose(m[d], o.mass(), rtol=1e-12)
 
 
+def _edge_cases():
+    """The smallest domains the library accepts and the degenerate compositions."""
+    tiny = W.random_mixture(3, 3, seed=21, walls=False)        # 3 x 3, periodic on both axes
+    slab = W.random_mixture(3, 5, seed=22, walls=True)         # walls: 3 fluid rows; x narrower than the halo
+    ragged = W.random_mixture(5, 4, seed=23, walls=False)
+    one = W.random_mixture(37, 19, seed=24, walls=True, circles=[(18.3, 9.6, 4.2)])
+    r = one.rho_init.copy()
+    r[0] = r.sum(0)
+    r[1:] = 0.0
+    one = one.with_params(name="fluid1_only", rho_init=r)      # one fluid: no colour gradient anywhere
+    two = W.random_mixture(41, 23, seed=25, walls=True, circles=[(20.5, 11.1, 5.0)])
+    r = two.rho_init.copy()
+    r[0] += r[2]
+    r[2] = 0.0
+    two = two.with_params(name="fluid3_absent", rho_init=r)    # two fluids: pairs 13 and 23 vanish
+    return [tiny, slab, ragged, one, two]
+
+
+@pytest.mark.parametrize("kernel", ["tile", "tile512"])
+def test_tiny_and_degenerate_domains_match_oracles(kernel):
+    """Domains of 3 x 3, 3 x 5 and 5 x 4 nodes (one partial tile, halos that wrap the periodic axes
+    more than once) and the single-fluid and two-fluid limits, each alone and all five in one
+    batched launch, against their oracles after 50 FP64 steps."""
+    lbm3 = _lbm3()
+    ws = _edge_cases()
+    refs = []
+    for w in ws:
+        o = po.Oracle(w)
+        o.step(50)
+        refs.append((o.rho(), np.array(o.mass())))
+    for w, (ref, mass) in zip(ws, refs):
+        print(f"case {w.name} {w.nx}x{w.ny} f64 {kernel} alone", flush=True)
+        sim = lbm3.Simulation(w, precision="f64", kernel=kernel)
+        sim.step(50)
+        r = sim.fields()["rho"].cpu().numpy()
+        assert np.abs(r - ref)[:, w.solid == 0].max() <= 1e-10, w.name
+        np.testing.assert_allclose(sim.mass()[0], mass, rtol=1e-12, atol=1e-9)
+        sim.close()
+    print(f"case edge batch of {len(ws)} f64 {kernel}", flush=True)
+    sim = lbm3.Simulation(ws, precision="f64", kernel=kernel)
+    sim.step(50)
+    m = sim.mass()
+    for d, (w, (ref, mass)) in enumerate(zip(ws, refs)):
+        r = sim.fields(d)["rho"].cpu().numpy()
+        assert np.abs(r - ref)[:, w.solid == 0].max() <= 1e-10, w.name
+        np.testing.assert_allclose(m[d], mass, rtol=1e-12, atol=1e-9)
+    sim.close()
+
+
 @pytest.mark.parametrize("precision", ["f64", "f32", "f16"])
 def test_execution_variants_are_bitwise_identical(precision):
     """The per-node arithmetic does not depend on the kernel family (tiles of 256 or 512 threads,
