@@ -105,11 +105,18 @@ typedef struct {
                                 unused */
   int32_t persistent_blocks; /* > 0: the fused kernel runs this many work-groups that loop over
                                 the (domain, tile) work list; 0: one work-group per work item */
-  int32_t adjoint;           /* 1: also lay out the scratch of the adjoint step (lbm3_adjoint_*);
-                                LBM3_F64 and LBM3_F32 only; 0: forward only */
+  int32_t adjoint;           /* 1: also lay out the scratch of the adjoint step (lbm3_adjoint_*,
+                                lbm3_loss_seed); LBM3_F64 and LBM3_F32 only; 0: forward only */
+  const char *tune_cache;    /* path of the autotuner's JSON cache (NULL = none): lbm3_autotune
+                                takes a configuration stored there for the same device
+                                architecture, precision and domain shapes without timing, and
+                                stores what it times; copied at creation */
 } lbm3_options;
 
-/* Bytes of device workspace lbm3_create needs for n domains (d[0..n-1]) and these options. */
+/* Bytes of device workspace lbm3_create needs for n domains (d[0..n-1]) and these options: the
+ * state of Sec. II A in its compact form (total distributions and partial densities, Eq. 13 and
+ * 16), twice, and the boundary tables of Sec. II B.  Host only; LBM3_EINVAL with
+ * lbm3_plan_error() on an invalid description (the checks of lbm3_create). */
 lbm3_status lbm3_workspace_bytes(const lbm3_domain *d, int32_t n, const lbm3_options *o,
                                  size_t *bytes);
 
@@ -122,7 +129,11 @@ lbm3_status lbm3_workspace_bytes(const lbm3_domain *d, int32_t n, const lbm3_opt
 lbm3_status lbm3_create(const lbm3_domain *d, int32_t n, const lbm3_options *o,
                         void *dev_workspace, size_t bytes, void *hip_stream, lbm3_ctx **out);
 
-/* Advances every domain by nsteps time steps (asynchronous). */
+/* Advances every domain by nsteps time steps of Sec. II: the wetting fill (Eq. 19-22), colour
+ * gradients and interfacial force (Eq. 10-12), MRT collision with forcing (Eq. 1-9, 11),
+ * recolouring (Eq. 13-15) and streaming with the boundary rules (Eq. 16, Sec. III).
+ * Asynchronous on the context's stream; with graph_block_steps > 0, whole blocks of steps are
+ * replayed from a captured hipGraph.  LBM3_EINVAL for nsteps < 0; LBM3_EHIP if a launch fails. */
 lbm3_status lbm3_step(lbm3_ctx *c, int32_t nsteps);
 
 /* Writes fields of the current state of domain `domain` into caller device buffers of element
@@ -138,17 +149,19 @@ lbm3_status lbm3_step(lbm3_ctx *c, int32_t nsteps);
 lbm3_status lbm3_fields(lbm3_ctx *c, int32_t domain, void *dev_rho, void *dev_u,
                         void *dev_force, int32_t dtype);
 
-/* Per-fluid mass sum_x rho_k over fluid nodes, in FP64 and a fixed summation order, for every
- * domain: host_out[3*n].  Synchronises.  Returns LBM3_ENUMERIC if a NaN/Inf was found. */
+/* Per-fluid mass sum_x rho_k over fluid nodes (rho_k = sum_a f_{a,k}, Eq. 16; conserved by
+ * recolouring, Eq. 13, and by the closed boundaries), in FP64 and a fixed summation order, for
+ * every domain: host_out[3*n].  Synchronises.  Returns LBM3_ENUMERIC if a NaN/Inf was found. */
 lbm3_status lbm3_mass(lbm3_ctx *c, double *host_out);
 
-/* Checkpointing of the whole state (all domains): a device-to-device copy of the raw state
- * planes.  set_state(get_state(s)) continues bit-identically. */
+/* Checkpointing of the whole state (all domains; the compact state of Eq. 13 and 16): a
+ * device-to-device copy of the raw state planes, lbm3_state_bytes long, into / from a caller
+ * buffer.  set_state(get_state(s)) continues bit-identically.  Asynchronous. */
 lbm3_status lbm3_state_bytes(const lbm3_ctx *c, size_t *bytes);
 lbm3_status lbm3_get_state(lbm3_ctx *c, void *dev_dst);
 lbm3_status lbm3_set_state(lbm3_ctx *c, const void *dev_src);
 
-/* Changes the wetting and tension parameters of domain `domain` (theta_deg[2] = theta13,
+/* Changes the wetting (Sec. II B) and tension (Eq. 10) parameters of domain `domain` (theta_deg[2] = theta13,
  * theta23 in degrees; sigma[3] = sigma12, sigma13, sigma23) with the checks of lbm3_create:
  * Eq. (18) fixes theta12 and Eq. (15) the factors g(X_kl).  The state is kept.  Synchronises. */
 lbm3_status lbm3_set_params(lbm3_ctx *c, int32_t domain, const double *theta_deg, const double *sigma);
@@ -170,6 +183,17 @@ lbm3_status lbm3_set_params(lbm3_ctx *c, int32_t domain, const double *theta_deg
  * ignored.  Asynchronous. */
 lbm3_status lbm3_adjoint_seed(lbm3_ctx *c, const double *dev_grad_rho, void *dev_lambda);
 
+/* Starts a backward pass for the phase-field mismatch loss of the inverse problem (the loss of
+ * the differentiation form; the mass fractions C_k = rho_k / rho of Eq. 16):
+ *   L_d = sum over the fluid nodes of domain d of sum_k (C_k - C*_k)^2
+ * of the context's current state.  Clears the parameter-gradient accumulators, writes
+ * lambda_T = dL/ds_T into dev_adj (a device buffer of lbm3_state_bytes in the state layout:
+ * dL/drho_k = (2/rho) [(C_k - C*_k) - sum_l C_l (C_l - C*_l)] at fluid nodes, zero elsewhere and in
+ * the distribution part) and the losses into dev_loss[n] (device, FP64, summed in a fixed order).
+ * dev_target_C: device, FP64, the domains' [3][ny][nx] target fractions concatenated in domain
+ * order (values at solid nodes ignored).  Needs options.adjoint = 1.  Asynchronous. */
+lbm3_status lbm3_loss_seed(lbm3_ctx *c, const double *dev_target_C, void *dev_adj, double *dev_loss);
+
 /* One step back: from the forward state s_t (dev_state, as written by lbm3_get_state) and
  * lambda_{t+1} (dev_lambda_in) writes lambda_t (dev_lambda_out, a different buffer) and adds
  * step t's parameter partials to the accumulators.  Leaves the context's own state alone.
@@ -182,7 +206,8 @@ lbm3_status lbm3_adjoint_step(lbm3_ctx *c, const void *dev_state, const void *de
  * (Eq. 15) included.  Synchronises. */
 lbm3_status lbm3_adjoint_grad(lbm3_ctx *c, double *host_grad);
 
-/* Average device time (ms) of one launch of the wetting-fill kernel and of the fused step kernel:
+/* Average device time (ms) of one launch of the wetting-fill kernel (Eq. 19-22) and of the fused
+ * step kernel (Eq. 1-16):
  * HIP events on the context's stream around nsteps back-to-back fills of the current state and
  * then nsteps back-to-back fused launches that all compute the same next step into the spare
  * buffer.  The state does not advance.  Synchronises. */
@@ -190,20 +215,27 @@ lbm3_status lbm3_kernel_times(lbm3_ctx *c, int32_t nsteps, double *ms_fill, doub
 
 /* Times the candidate configurations of the fused kernel (tile shapes, strip widths and
  * segment lengths) on the live state and keeps the fastest; returns (kernel, tile_x, tile_y)
- * in choice[3].  Every candidate computes the same result bit for bit; each candidate's two
- * warm-up steps advance the state.  Synchronises. */
+ * in choice[3].  Every candidate computes the same result bit for bit (the step of Sec. II);
+ * each candidate's two warm-up steps advance the state.  With options.tune_cache, a stored
+ * choice for this device, precision and set of domain shapes is taken without timing (the state
+ * does not advance), and a timed choice is stored (LBM3_EINVAL if the file cannot be written).
+ * Synchronises. */
 lbm3_status lbm3_autotune(lbm3_ctx *c, int32_t steps_per_candidate, int32_t *choice);
 
-/* Information: key 0 = algorithmic bytes per lattice update of the fused kernel (state read
+/* Information about the step of Sec. II: key 0 = algorithmic bytes per lattice update of the
+ * fused kernel (state read
  * once and written once), 1 = total nodes, 2 = fill nodes, 3 = interpolated-bounce-back nodes,
  * 4 = tile_x, 5 = tile_y, 6 = work items, 7 = steps taken, 8 = kernel (0/3 tiles of 256/512
  * threads, 1/2 strips). */
 lbm3_status lbm3_query(const lbm3_ctx *c, int32_t key, double *value);
 
+/* Status text: the message of the last failure on a context (never NULL; the string lives until
+ * the next call on that context). */
 const char *lbm3_last_error(const lbm3_ctx *c);
 /* Message of the last failed lbm3_workspace_bytes or lbm3_create on the calling thread (those
  * calls have no context to attach it to). */
 const char *lbm3_plan_error(void);
+/* Short text of an lbm3_status code (static storage). */
 const char *lbm3_status_string(int32_t code);
 
 /* Frees host bookkeeping, graphs and events; never frees the caller's workspace. */

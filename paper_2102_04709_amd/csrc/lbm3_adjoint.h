@@ -65,4 +65,13 @@ template <typename T>
 hipError_t launch_adjoint_seed(const DomainDev *doms, const WorkItem *work, int n_work, const uint8_t *flags,
                                const double *g, T *lam, int64_t tplane, hipStream_t s);
 
+// Phase-field mismatch loss of the state (rho: its density planes) against target (flat
+// [3][ny][nx] FP64 per domain): writes dL/drho_k into the density planes of lam at fluid nodes,
+// one loss partial per tile into part[n_work], and the per-domain losses into loss[n_dom]
+// (tiles first[d] .. first[d+1]-1 belong to domain d); work = 32 x 8 tiles over the real nodes.
+template <typename T>
+hipError_t launch_loss_seed(const DomainDev *doms, const WorkItem *work, int n_work, const int *first, int n_dom,
+                            const uint8_t *flags, const T *rho, int64_t tplane, const double *target, T *lam,
+                            double *part, double *loss, hipStream_t s);
+
 }  // namespace lbm3

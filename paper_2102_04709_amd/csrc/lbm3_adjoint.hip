@@ -837,6 +837,59 @@ __global__ __launch_bounds__(kThreads) void adj_seed(const DomainDev *doms, cons
   for (int k = 0; k < 3; ++k) lam[9 * tplane + 3 * D.base + k * D.plane + li] = (T)g[o + k * n];
 }
 
+// Phase-field mismatch loss L = sum over fluid nodes of sum_k (C_k - C*_k)^2 with C_k = rho_k /
+// rho (the loss of the inverse problem), and its gradient with respect to the partial densities,
+// dL/drho_k = (2 / rho) [(C_k - C*_k) - sum_l C_l (C_l - C*_l)], written into the density planes of
+// lam at fluid nodes.  FP64 throughout; each work-group writes its loss partial (fixed order
+// inside the group) to part[blockIdx.x], and loss_final sums a domain's partials in tile order,
+// so the loss is reproducible bit for bit.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void loss_seed_tiles(const DomainDev *doms, const WorkItem *work,
+                                                            const uint8_t *flags, const T *rho, int64_t tplane,
+                                                            const double *target, T *lam, double *part) {
+  const WorkItem wk = work[blockIdx.x];
+  const DomainDev &D = doms[wk.dom];
+  int i, j;
+  double l = 0.0;
+  if (tile_node(wk, i, j) && fluid_node(flags, D, i, j)) {
+    const int64_t li = plane_index(i, j, D.pitch);
+    const T *R = rho + 3 * D.base;
+    const int64_t n = (int64_t)D.nx * D.ny, o = D.goff + (int64_t)j * D.nx + i;
+    double r[3], c[3], d[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) r[k] = (double)R[k * D.plane + li];
+    const double rt = r[0] + r[1] + r[2];
+    double m = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      c[k] = r[k] / rt;
+      d[k] = c[k] - target[o + k * n];
+      l += d[k] * d[k];
+      m += c[k] * d[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) lam[9 * tplane + 3 * D.base + k * D.plane + li] = (T)(2.0 * (d[k] - m) / rt);
+  }
+  __shared__ double red[kThreads / 64];
+  const double s = wave_sum(l);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < kThreads / 64; ++q) t += red[q];
+    part[blockIdx.x] = t;
+  }
+}
+
+__global__ void loss_final(const double *part, const int *first, int n_dom, double *loss) {
+  const int d = blockIdx.x * blockDim.x + threadIdx.x;
+  if (d >= n_dom) return;
+  double s = 0.0;
+  for (int b = first[d]; b < first[d + 1]; ++b) s += part[b];
+  loss[d] = s;
+}
+
 // ---- launchers -----------------------------------------------------------------------------
 template <typename S, typename T>
 hipError_t launch_adjoint(const AdjArgs<S, T> &a, int64_t tplane, hipStream_t s) {
@@ -857,11 +910,29 @@ hipError_t launch_adjoint_seed(const DomainDev *doms, const WorkItem *work, int 
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_loss_seed(const DomainDev *doms, const WorkItem *work, int n_work, const int *first, int n_dom,
+                            const uint8_t *flags, const T *rho, int64_t tplane, const double *target, T *lam,
+                            double *part, double *loss, hipStream_t s) {
+  if (n_work > 0)
+    hipLaunchKernelGGL((loss_seed_tiles<T>), dim3(n_work), dim3(kThreads), 0, s, doms, work, flags, rho, tplane, target,
+                       lam, part);
+  hipLaunchKernelGGL(loss_final, dim3((n_dom + 63) / 64), dim3(64), 0, s, part, first, n_dom, loss);
+  return hipGetLastError();
+}
+
 template hipError_t launch_adjoint<double, double>(const AdjArgs<double, double> &, int64_t, hipStream_t);
 template hipError_t launch_adjoint<float, float>(const AdjArgs<float, float> &, int64_t, hipStream_t);
 template hipError_t launch_adjoint_seed<double>(const DomainDev *, const WorkItem *, int, const uint8_t *,
                                                 const double *, double *, int64_t, hipStream_t);
 template hipError_t launch_adjoint_seed<float>(const DomainDev *, const WorkItem *, int, const uint8_t *,
                                                const double *, float *, int64_t, hipStream_t);
+
+template hipError_t launch_loss_seed<double>(const DomainDev *, const WorkItem *, int, const int *, int,
+                                             const uint8_t *, const double *, int64_t, const double *, double *,
+                                             double *, double *, hipStream_t);
+template hipError_t launch_loss_seed<float>(const DomainDev *, const WorkItem *, int, const int *, int,
+                                            const uint8_t *, const float *, int64_t, const double *, float *,
+                                            double *, double *, hipStream_t);
 
 }  // namespace lbm3

@@ -70,7 +70,7 @@ struct DomHost {
 struct Layout {
   size_t off_F[2], off_R[2], off_flags, off_fill, off_fillC, off_ibb, off_doms, off_work, off_fwork, off_partial,
       off_chunk_dom, off_chunk_first, off_mass, off_bad, off_aX, off_awork, off_raw, off_tibb, off_fblk, off_ibbof,
-      off_links, off_far, total;
+      off_links, off_far, off_lpart, off_lfirst, total;
   int64_t total_plane;
   int64_t aplane;  // elements of one adjoint scratch plane (all domains' extended grids)
   int n_fill, n_ibb, n_chunks, max_work, n_fwork, n_awork, n_fblk;
@@ -451,13 +451,15 @@ bool plan(const lbm3_domain *d, int n, const lbm3_options *o, std::vector<DomHos
   L.off_chunk_first = take(sizeof(int) * (n + 1));
   L.off_mass = take(sizeof(double) * 3 * n);
   L.off_bad = take(sizeof(int));
-  L.off_aX = L.off_awork = L.off_raw = L.off_ibbof = L.off_links = 0;
+  L.off_aX = L.off_awork = L.off_raw = L.off_ibbof = L.off_links = L.off_lpart = L.off_lfirst = 0;
   if (o->adjoint) {
     L.off_aX = take((size_t)A_PLANES * (size_t)abase * t_size(prec));
     L.off_awork = take(sizeof(WorkItem) * naw);
     L.off_raw = take(sizeof(double) * 9 * n);
     L.off_ibbof = take(sizeof(int32_t) * (size_t)base);
     L.off_links = take(sizeof(uint32_t) * (size_t)base);
+    L.off_lpart = take(sizeof(double) * (size_t)std::max(nfw, 1));
+    L.off_lfirst = take(sizeof(int) * (size_t)(n + 1));
   }
   L.total = off;
   return true;
@@ -467,6 +469,8 @@ bool plan(const lbm3_domain *d, int n, const lbm3_options *o, std::vector<DomHos
 
 struct lbm3_ctx {
   int n = 0;
+  int device = 0;               // the GPU current at creation
+  std::string tune_cache;       // lbm3_options.tune_cache ("" = none)
   int precision = 0;
   hipStream_t stream = nullptr;
   hipStream_t cap_stream = nullptr;
@@ -836,6 +840,86 @@ lbm3_status time_kernels_t(lbm3_ctx *c, int n, hipEvent_t ev[3]) {
   return LBM3_OK;
 }
 
+// ---- autotuner cache --------------------------------------------------------------------
+// A JSON object with one line per entry,
+//   "<key>": {"kernel": K, "tile_x": X, "tile_y": Y, "ms_per_step": T},
+// keyed by the device architecture, the precision and the domains' shapes and boundary types
+// (their count, total nodes and an FNV-1a hash of nx, ny, y_periodic, bc_x, fill and curved-node
+// counts of every domain).  The configurations compute identical results, so a stale entry can
+// only cost time.
+struct TuneEntry {
+  std::string key;
+  int kernel, tx, ty;
+  double ms;
+};
+
+std::string tune_key(const lbm3_ctx *c) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](int64_t v) {
+    for (int b = 0; b < 8; ++b) {
+      h ^= (uint64_t)((v >> (8 * b)) & 0xff);
+      h *= 1099511628211ull;
+    }
+  };
+  int64_t nodes = 0;
+  for (const DomainDev &D : c->doms) {
+    mix(D.nx); mix(D.ny); mix(D.yper); mix(D.bcx); mix(D.n_fill); mix(D.n_ibb);
+    nodes += (int64_t)D.nx * D.ny;
+  }
+  hipDeviceProp_t prop;
+  const char *arch = hipGetDeviceProperties(&prop, c->device) == hipSuccess ? prop.gcnArchName : "unknown";
+  std::string a(arch);
+  const size_t colon = a.find(':');
+  if (colon != std::string::npos) a = a.substr(0, colon);
+  const char *prec = c->precision == LBM3_F64 ? "f64" : (c->precision == LBM3_F32 ? "f32" : "f32-f16store");
+  char b[256];
+  snprintf(b, sizeof b, "%s %s domains=%d nodes=%lld shapes=%016llx", a.c_str(), prec, c->n, (long long)nodes,
+           (unsigned long long)h);
+  return b;
+}
+
+std::vector<TuneEntry> read_tune_cache(const std::string &path) {
+  std::vector<TuneEntry> out;
+  FILE *f = fopen(path.c_str(), "r");
+  if (!f) return out;
+  char line[1024];
+  while (fgets(line, sizeof line, f)) {
+    const char *q0 = strchr(line, '"');
+    if (!q0) continue;
+    const char *q1 = strchr(q0 + 1, '"');
+    if (!q1) continue;
+    TuneEntry e;
+    e.key.assign(q0 + 1, q1);
+    if (sscanf(q1 + 1, ": {\"kernel\": %d, \"tile_x\": %d, \"tile_y\": %d, \"ms_per_step\": %lf", &e.kernel, &e.tx,
+               &e.ty, &e.ms) == 4)
+      out.push_back(e);
+  }
+  fclose(f);
+  return out;
+}
+
+bool write_tune_cache(const std::string &path, const TuneEntry &add) {
+  std::vector<TuneEntry> entries = read_tune_cache(path);
+  bool found = false;
+  for (TuneEntry &e : entries)
+    if (e.key == add.key) {
+      e = add;
+      found = true;
+    }
+  if (!found) entries.push_back(add);
+  const std::string tmp = path + ".tmp";
+  FILE *f = fopen(tmp.c_str(), "w");
+  if (!f) return false;
+  fprintf(f, "{\n");
+  for (size_t i = 0; i < entries.size(); ++i)
+    fprintf(f, "  \"%s\": {\"kernel\": %d, \"tile_x\": %d, \"tile_y\": %d, \"ms_per_step\": %.6g}%s\n",
+            entries[i].key.c_str(), entries[i].kernel, entries[i].tx, entries[i].ty, entries[i].ms,
+            i + 1 < entries.size() ? "," : "");
+  fprintf(f, "}\n");
+  const bool ok = fclose(f) == 0;
+  return ok && rename(tmp.c_str(), path.c_str()) == 0;
+}
+
 }  // namespace
 
 extern "C" {
@@ -910,6 +994,9 @@ lbm3_status lbm3_create(const lbm3_domain *d, int32_t n, const lbm3_options *o, 
   };
   hipError_t e = init_kernel_attributes();
   if (e != hipSuccess) return bail(hip_fail(c, e, "hipFuncSetAttribute"));
+  e = hipGetDevice(&c->device);
+  if (e != hipSuccess) return bail(hip_fail(c, e, "hipGetDevice"));
+  if (o->tune_cache) c->tune_cache = o->tune_cache;
   e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
   if (e != hipSuccess) return bail(hip_fail(c, e, "hipStreamCreateWithFlags"));
   c->hflags.assign((size_t)L.total_plane, 0);
@@ -994,6 +1081,12 @@ lbm3_status lbm3_create(const lbm3_domain *d, int32_t n, const lbm3_options *o, 
   }
   CK(hipMemcpyAsync(c->at<void>(L.off_chunk_dom), chunk_dom.data(), sizeof(int) * chunk_dom.size(), hipMemcpyHostToDevice, s));
   CK(hipMemcpyAsync(c->at<void>(L.off_chunk_first), chunk_first.data(), sizeof(int) * chunk_first.size(), hipMemcpyHostToDevice, s));
+  std::vector<int> lfirst;  // adjoint only: first field tile of each domain (loss partials)
+  if (c->adjoint) {
+    for (int i = 0; i < n; ++i) lfirst.push_back(c->fwork_off[i]);
+    lfirst.push_back((int)c->fwork.size());
+    CK(hipMemcpyAsync(c->at<void>(L.off_lfirst), lfirst.data(), sizeof(int) * lfirst.size(), hipMemcpyHostToDevice, s));
+  }
   CK(hipMemsetAsync(c->at<void>(L.off_bad), 0, sizeof(int), s));
 #undef CK
   lbm3_status st = upload_tables(c);  // synchronises the stream
@@ -1153,6 +1246,32 @@ lbm3_status lbm3_adjoint_seed(lbm3_ctx *c, const double *dev_grad_rho, void *dev
   return LBM3_OK;
 }
 
+lbm3_status lbm3_loss_seed(lbm3_ctx *c, const double *dev_target_C, void *dev_adj, double *dev_loss) {
+  lbm3_status st = adjoint_ready(c);
+  if (st != LBM3_OK) return st;
+  if (!dev_target_C || !dev_adj || !dev_loss) {
+    c->err = "missing buffer";
+    return LBM3_EINVAL;
+  }
+  size_t bytes = 0;
+  (void)lbm3_state_bytes(c, &bytes);
+  HIPC(c, hipMemsetAsync(dev_adj, 0, bytes, c->stream));
+  HIPC(c, hipMemsetAsync(c->at<void>(c->L.off_raw), 0, sizeof(double) * 9 * c->n, c->stream));
+  const DomainDev *doms = c->at<DomainDev>(c->L.off_doms);
+  const WorkItem *w = c->at<WorkItem>(c->L.off_fwork);
+  const uint8_t *fl = c->at<uint8_t>(c->L.off_flags);
+  const int *first = c->at<int>(c->L.off_lfirst);
+  double *part = c->at<double>(c->L.off_lpart);
+  const int nw = (int)c->fwork.size();
+  if (c->precision == LBM3_F64)
+    HIPC(c, launch_loss_seed<double>(doms, w, nw, first, c->n, fl, c->at<double>(c->L.off_R[c->cur]), c->L.total_plane,
+                                     dev_target_C, reinterpret_cast<double *>(dev_adj), part, dev_loss, c->stream));
+  else
+    HIPC(c, launch_loss_seed<float>(doms, w, nw, first, c->n, fl, c->at<float>(c->L.off_R[c->cur]), c->L.total_plane,
+                                    dev_target_C, reinterpret_cast<float *>(dev_adj), part, dev_loss, c->stream));
+  return LBM3_OK;
+}
+
 lbm3_status lbm3_adjoint_step(lbm3_ctx *c, const void *dev_state, const void *dev_lambda_in, void *dev_lambda_out) {
   lbm3_status st = adjoint_ready(c);
   if (st != LBM3_OK) return st;
@@ -1211,7 +1330,20 @@ lbm3_status lbm3_autotune(lbm3_ctx *c, int32_t steps_per_candidate, int32_t *cho
   if (!c || steps_per_candidate < 1) return LBM3_EINVAL;
   double best = 1e300;
   Candidate bc{c->mode, c->tx, c->ty};
+  const std::string key = c->tune_cache.empty() ? std::string() : tune_key(c);
+  bool cached = false;
+  if (!key.empty()) {
+    const std::vector<TuneEntry> entries = read_tune_cache(c->tune_cache);
+    for (const TuneEntry &e : entries)
+      if (e.key == key)
+        for (const Candidate &t : kCands)
+          if (t.kernel == e.kernel && t.tx == e.tx && t.ty == e.ty) {
+            bc = t;
+            cached = true;
+          }
+  }
   for (const Candidate &t : kCands) {
+    if (cached) break;
     if (is_tile_mode(t.kernel) && step_smem_bytes(c->precision, t.kernel, t.tx, t.ty) > 160 * 1024) continue;
     if (!is_tile_mode(t.kernel) && step_smem_bytes(c->precision, t.kernel, 0, 0) > 160 * 1024) continue;
     c->mode = t.kernel;
@@ -1238,6 +1370,10 @@ lbm3_status lbm3_autotune(lbm3_ctx *c, int32_t steps_per_candidate, int32_t *cho
   c->graph_valid = false;
   lbm3_status st = upload_tables(c);
   if (st != LBM3_OK) return st;
+  if (!key.empty() && !cached && !write_tune_cache(c->tune_cache, TuneEntry{key, bc.kernel, bc.tx, bc.ty, best})) {
+    c->err = "lbm3_autotune: cannot write the tune cache " + c->tune_cache;
+    return LBM3_EINVAL;
+  }
   if (choice) {
     choice[0] = bc.kernel;
     choice[1] = bc.tx;

@@ -27,6 +27,7 @@ ABI_SYMBOLS = [
     "lbm3_state_bytes", "lbm3_get_state", "lbm3_set_state", "lbm3_kernel_times", "lbm3_autotune",
     "lbm3_query", "lbm3_last_error", "lbm3_plan_error", "lbm3_status_string", "lbm3_destroy",
     "lbm3_set_params", "lbm3_adjoint_seed", "lbm3_adjoint_step", "lbm3_adjoint_grad",
+    "lbm3_loss_seed",
 ]
 
 
@@ -47,6 +48,7 @@ class lbm3_options(C.Structure):
         ("precision", C.c_int32), ("graph_block_steps", C.c_int32), ("beta0", C.c_double),
         ("kernel", C.c_int32), ("tile_x", C.c_int32), ("tile_y", C.c_int32),
         ("persistent_blocks", C.c_int32), ("adjoint", C.c_int32),
+        ("tune_cache", C.c_char_p),
     ]
 
 
@@ -91,6 +93,7 @@ def library() -> C.CDLL:
             "lbm3_adjoint_seed": (i32, [vp, vp, vp]),
             "lbm3_adjoint_step": (i32, [vp, vp, vp, vp]),
             "lbm3_adjoint_grad": (i32, [vp, dp]),
+            "lbm3_loss_seed": (i32, [vp, vp, vp, vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -128,7 +131,7 @@ class DomainArgs:
 
 
 def make_options(precision="f32", graph_block_steps=0, beta0=0.0, tile=None, persistent_blocks=0,
-                 kernel="tile", adjoint=False):
+                 kernel="tile", adjoint=False, tune_cache=None):
     o = lbm3_options()
     o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     o.graph_block_steps = int(graph_block_steps)
@@ -137,6 +140,7 @@ def make_options(precision="f32", graph_block_steps=0, beta0=0.0, tile=None, per
     o.tile_x, o.tile_y = (0, 0) if tile is None else (int(tile[0]), int(tile[1]))
     o.persistent_blocks = int(persistent_blocks)
     o.adjoint = 1 if adjoint else 0
+    o.tune_cache = os.fsencode(tune_cache) if tune_cache else None
     return o
 
 
@@ -224,6 +228,10 @@ def lbm3_adjoint_seed(ctx, grad_rho_ptr: int, lam_ptr: int) -> None:
     _check(library().lbm3_adjoint_seed(ctx, C.c_void_p(grad_rho_ptr), C.c_void_p(lam_ptr)), ctx)
 
 
+def lbm3_loss_seed(ctx, target_ptr: int, lam_ptr: int, loss_ptr: int) -> None:
+    _check(library().lbm3_loss_seed(ctx, C.c_void_p(target_ptr), C.c_void_p(lam_ptr), C.c_void_p(loss_ptr)), ctx)
+
+
 def lbm3_adjoint_step(ctx, state_ptr: int, lam_in_ptr: int, lam_out_ptr: int) -> None:
     _check(library().lbm3_adjoint_step(ctx, C.c_void_p(state_ptr), C.c_void_p(lam_in_ptr),
                                        C.c_void_p(lam_out_ptr)), ctx)
@@ -241,7 +249,8 @@ class Simulation:
     """Domains advanced together on one GPU by liblbm3."""
 
     def __init__(self, workloads, precision="f32", graph_block_steps=0, tile=None,
-                 persistent_blocks=0, beta0=0.0, device="cuda:0", kernel="tile", adjoint=False):
+                 persistent_blocks=0, beta0=0.0, device="cuda:0", kernel="tile", adjoint=False,
+                 tune_cache=None):
         import torch
 
         if not isinstance(workloads, (list, tuple)):
@@ -251,13 +260,15 @@ class Simulation:
         self.device = torch.device(device)
         self.domains = DomainArgs(self.workloads)
         self.options = make_options(precision, graph_block_steps, beta0, tile, persistent_blocks, kernel,
-                                    adjoint)
+                                    adjoint, tune_cache)
         nbytes = lbm3_workspace_bytes(self.domains, self.options)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self.stream = torch.cuda.current_stream(self.device)
         self.ctx = lbm3_create(self.domains, self.options, self.workspace.data_ptr(), nbytes,
                                self.stream.cuda_stream)
         self.n = len(self.workloads)
+        # the wetting and tension parameters in force (theta13, theta23, sigma12, sigma13, sigma23)
+        self.params = np.array([[*w.theta_deg, *w.sigma] for w in self.workloads], dtype=np.float64)
 
     @property
     def field_dtype(self):
@@ -304,6 +315,7 @@ class Simulation:
 
     def set_params(self, domain: int, theta_deg, sigma) -> None:
         lbm3_set_params(self.ctx, domain, theta_deg, sigma)
+        self.params[domain] = [*theta_deg, *sigma]
 
     def densities(self):
         """Partial densities of every domain, flat [3][ny][nx] per domain concatenated, zero at
@@ -321,6 +333,18 @@ class Simulation:
         g = grad_rho.to(device=self.device, dtype=torch.float64).contiguous()
         assert lam.numel() == self.state_bytes() and lam.is_contiguous()
         lbm3_adjoint_seed(self.ctx, g.data_ptr(), lam.data_ptr())
+
+    def loss_seed(self, target, lam):
+        """Phase-field mismatch loss of the current state against target (flat [3][ny][nx] per
+        domain, FP64) on the device; writes lambda_T into lam and returns the per-domain losses
+        (device tensor [n], FP64)."""
+        import torch
+        t = target.to(device=self.device, dtype=torch.float64).contiguous()
+        assert t.numel() == sum(3 * w.nx * w.ny for w in self.workloads)
+        assert lam.numel() == self.state_bytes() and lam.is_contiguous()
+        loss = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        lbm3_loss_seed(self.ctx, t.data_ptr(), lam.data_ptr(), loss.data_ptr())
+        return loss
 
     def adjoint_step(self, state, lam_in, lam_out) -> None:
         n = self.state_bytes()

@@ -5,10 +5,17 @@ torch.autograd.Function, with checkpoint-and-recompute.
 `sim` (an lbm3.Simulation created with adjoint=True) from `init_state` with the wetting and
 tension parameters `params` ([n_domains, 5]: theta13, theta23 in degrees, sigma12, sigma13,
 sigma23) and returns the partial densities at the last step (flat, [3][ny][nx] per domain,
-zero at solid nodes).  Its backward pass gives dL/dparams for any loss L of those densities:
-the forward keeps a state checkpoint every `every` steps; the backward replays each block from
-its checkpoint, keeping the block's states, and runs the hand-written adjoint step
-(lbm3_adjoint_step) backwards through it.  Device memory: (steps / every + every) states.
+zero at solid nodes).  Its backward pass gives dL/dparams for any loss L of those densities.
+
+`rollout_loss(params, sim, steps, init_state, target, every)` returns the phase-field mismatch
+loss sum_k sum_fluid (C_k - C*_k)^2 per domain ([n_domains]), formed on the device by
+lbm3_loss_seed, which also seeds the backward pass.
+
+Both keep a state checkpoint every `every` steps in the forward pass; the backward pass replays
+each block from its checkpoint, keeping the block's states, and runs the hand-written adjoint
+step (lbm3_adjoint_step) backwards through it.  Device memory: (steps / every + every) states.
+The backward pass runs at the parameters of its own forward pass (whatever the Simulation was
+set to in between) and leaves the Simulation's parameters and state as it found them.
 """
 from __future__ import annotations
 
@@ -16,52 +23,108 @@ import numpy as np
 import torch
 
 
+def _forward(sim, p, steps, init_state, every):
+    for d in range(sim.n):
+        sim.set_params(d, p[d, :2], p[d, 2:])
+    sim.set_state(init_state)
+    ckpts = []
+    done = 0
+    while done < steps:
+        k = min(every, steps - done)
+        ckpts.append(sim.get_state())
+        sim.step(k)
+        done += k
+    return ckpts
+
+
+def _backward(sim, p, steps, every, ckpts, seed):
+    """Runs the adjoint through the blocks at parameters p; seed(lam) writes lambda_T.  Returns
+    the parameter gradient [n, 5] (float64, CPU) and restores the caller's parameters and state."""
+    saved_params = sim.params.copy()
+    resume = sim.get_state()
+    for d in range(sim.n):
+        sim.set_params(d, p[d, :2], p[d, 2:])
+    nb = sim.state_bytes()
+    lam = torch.empty(nb, dtype=torch.uint8, device=sim.device)
+    lam2 = torch.empty_like(lam)
+    seed(lam)
+    block = torch.empty((min(every, steps), nb), dtype=torch.uint8, device=sim.device)
+    for b in reversed(range(len(ckpts))):
+        k = min(every, steps - b * every)
+        sim.set_state(ckpts[b])
+        for t in range(k):
+            sim.get_state(out=block[t])
+            if t + 1 < k:
+                sim.step(1)
+        for t in reversed(range(k)):
+            sim.adjoint_step(block[t], lam, lam2)
+            lam, lam2 = lam2, lam
+    grad = sim.adjoint_grad()
+    for d in range(sim.n):
+        sim.set_params(d, saved_params[d, :2], saved_params[d, 2:])
+    sim.set_state(resume)
+    return grad
+
+
 class _Rollout(torch.autograd.Function):
     @staticmethod
     def forward(ctx, params, sim, steps, init_state, every):
-        p = params.detach().to("cpu", torch.float64).numpy().reshape(sim.n, 5)
-        for d in range(sim.n):
-            sim.set_params(d, p[d, :2], p[d, 2:])
-        sim.set_state(init_state)
-        ckpts = []
-        done = 0
-        while done < steps:
-            k = min(every, steps - done)
-            ckpts.append(sim.get_state())
-            sim.step(k)
-            done += k
+        p = params.detach().to("cpu", torch.float64).numpy().reshape(sim.n, 5).copy()
+        ckpts = _forward(sim, p, steps, init_state, every)
         out = sim.densities()
-        ctx.sim, ctx.steps, ctx.every, ctx.ckpts = sim, int(steps), int(every), ckpts
-        ctx.param_dtype = params.dtype
+        ctx.sim, ctx.steps, ctx.every, ctx.ckpts, ctx.p = sim, int(steps), int(every), ckpts, p
+        ctx.param_dtype, ctx.param_device = params.dtype, params.device
         return out
 
     @staticmethod
     def backward(ctx, grad_out):
-        sim, steps, every = ctx.sim, ctx.steps, ctx.every
-        nb = sim.state_bytes()
-        lam = torch.empty(nb, dtype=torch.uint8, device=sim.device)
-        lam2 = torch.empty_like(lam)
-        sim.adjoint_seed(grad_out, lam)
-        resume = sim.get_state()
-        block = torch.empty((min(every, steps), nb), dtype=torch.uint8, device=sim.device)
-        for b in reversed(range(len(ctx.ckpts))):
-            k = min(every, steps - b * every)
-            sim.set_state(ctx.ckpts[b])
-            for t in range(k):
-                sim.get_state(out=block[t])
-                if t + 1 < k:
-                    sim.step(1)
-            for t in reversed(range(k)):
-                sim.adjoint_step(block[t], lam, lam2)
-                lam, lam2 = lam2, lam
-        sim.set_state(resume)
-        grad = torch.as_tensor(sim.adjoint_grad(), dtype=ctx.param_dtype).reshape(sim.n, 5)
+        sim = ctx.sim
+        grad = _backward(sim, ctx.p, ctx.steps, ctx.every, ctx.ckpts,
+                         lambda lam: sim.adjoint_seed(grad_out, lam))
         ctx.ckpts = None
-        return grad, None, None, None, None
+        g = torch.as_tensor(grad, dtype=ctx.param_dtype).reshape(sim.n, 5).to(ctx.param_device)
+        return g, None, None, None, None
+
+
+class _RolloutLoss(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, params, sim, steps, init_state, target, every):
+        p = params.detach().to("cpu", torch.float64).numpy().reshape(sim.n, 5).copy()
+        ckpts = _forward(sim, p, steps, init_state, every)
+        scratch = torch.empty(sim.state_bytes(), dtype=torch.uint8, device=sim.device)
+        loss = sim.loss_seed(target, scratch)
+        ctx.sim, ctx.steps, ctx.every, ctx.ckpts, ctx.p = sim, int(steps), int(every), ckpts, p
+        ctx.final = sim.get_state()
+        ctx.target = target
+        ctx.param_dtype, ctx.param_device = params.dtype, params.device
+        return loss.to(params.device)
+
+    @staticmethod
+    def backward(ctx, grad_loss):
+        sim = ctx.sim
+        gl = grad_loss.detach().to("cpu", torch.float64).reshape(-1)
+
+        def seed(lam):
+            sim.set_state(ctx.final)
+            sim.loss_seed(ctx.target, lam)
+
+        # the domains are independent, so the gradient of sum_d g_d L_d is g_d times the
+        # gradient of L_d, domain by domain
+        grad = _backward(sim, ctx.p, ctx.steps, ctx.every, ctx.ckpts, seed) * gl.numpy()[:, None]
+        ctx.ckpts = ctx.final = None
+        g = torch.as_tensor(grad, dtype=ctx.param_dtype).reshape(sim.n, 5).to(ctx.param_device)
+        return g, None, None, None, None, None
 
 
 def rollout(params: torch.Tensor, sim, steps: int, init_state: torch.Tensor, every: int = 100) -> torch.Tensor:
     return _Rollout.apply(params, sim, steps, init_state, every)
+
+
+def rollout_loss(params: torch.Tensor, sim, steps: int, init_state: torch.Tensor, target: torch.Tensor,
+                 every: int = 100) -> torch.Tensor:
+    """Per-domain phase-field mismatch loss after `steps` steps (device-side, lbm3_loss_seed);
+    target: flat [3][ny][nx] per domain of target mass fractions."""
+    return _RolloutLoss.apply(params, sim, steps, init_state, target, every)
 
 
 def phase_fields(rho_flat: torch.Tensor, workloads):

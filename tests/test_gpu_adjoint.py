@@ -249,3 +249,114 @@ def test_inverse_problem_vs_oracle_fd(precision):
     print(f"adjoint {g}\noracle fd (h/10) {g_fd}", flush=True)
     assert abs(L - gold["loss"]) <= (1e-9 if precision == "f64" else 1e-4) * gold["loss"]
     assert err.max() <= INVERSE_TOL[precision]
+
+
+def _density_part(lam, ws, d):
+    """The density planes of domain d of a state-layout FP64 buffer: [3, ny, nx]."""
+    import torch
+    v = lam.view(torch.float64)
+    planes = [((w.nx + 63) // 64 * 64) * (w.ny + 4) for w in ws]
+    tplane, base = sum(planes), sum(planes[:d])
+    w = ws[d]
+    pitch = (w.nx + 63) // 64 * 64
+    out = []
+    for k in range(3):
+        o = 9 * tplane + 3 * base + k * planes[d]
+        out.append(v[o:o + planes[d]].reshape(w.ny + 4, pitch)[2:2 + w.ny, :w.nx])
+    return torch.stack(out).cpu().numpy()
+
+
+def test_loss_seed_vs_numpy():
+    """lbm3_loss_seed (the device loss of the inverse problem and its lambda_T) through the C ABI:
+    the loss against numpy on the GPU's own fields (1e-12) and on the oracle's fields (1e-10), and
+    lambda_T against dL/drho_k = (2/rho)[(C_k - C*_k) - sum_l C_l (C_l - C*_l)] written out in numpy
+    (1e-12), for two batched domains."""
+    torch, lbm3, rollout = _mods()
+    cases = small_cases()
+    ws = [cases["walls_circle"], cases["swap13"]]
+    steps = 20
+    targets = [oracle_C(target_setup(w), steps) for w in ws]
+    print("loss seed: 2 domains, f64, 20 steps", flush=True)
+    sim = lbm3.Simulation(ws, precision="f64", adjoint=True)
+    sim.step(steps)
+    tgt = torch.cat([torch.as_tensor(t).reshape(-1) for t in targets]).to(sim.device)
+    lam = torch.empty(sim.state_bytes(), dtype=torch.uint8, device=sim.device)
+    loss = sim.loss_seed(tgt, lam).cpu().numpy()
+    for d, (w, t) in enumerate(zip(ws, targets)):
+        rho = sim.fields(d, velocity=False, force=False)["rho"].cpu().numpy()
+        fl = w.solid == 0
+        tot = np.where(fl, rho.sum(0), 1.0)
+        C = np.where(fl, rho / tot, 0.0)
+        L_np = mismatch(C, t, w.solid)
+        L_or = mismatch(oracle_C(w, steps), t, w.solid)
+        print(f"domain {d}: loss device {loss[d]:.16e} numpy {L_np:.16e} oracle {L_or:.16e}", flush=True)
+        assert abs(loss[d] - L_np) <= 1e-12 * L_np
+        assert abs(loss[d] - L_or) <= 1e-10 * L_or
+        dC = C - t
+        m = (C * dC).sum(0)
+        lam_np = np.where(fl, 2.0 * (dC - m) / tot, 0.0)
+        got = _density_part(lam, ws, d)
+        err = np.abs(got - lam_np).max() / np.abs(lam_np).max()
+        print(f"domain {d}: lambda_T rel err {err:.3e}", flush=True)
+        assert err <= 1e-12
+    v = lam.view(torch.float64)
+    n9 = 9 * (v.numel() // 12)
+    assert float(v[:n9].abs().max()) == 0.0
+    sim.close()
+
+
+def test_rollout_loss_gradient_equals_rollout_gradient():
+    """rollout_loss (device loss, lambda_T from lbm3_loss_seed) and rollout + a torch loss give
+    the same parameter gradient; a weight on the loss scales it."""
+    torch, lbm3, rollout = _mods()
+    w = small_cases()["walls_circle"]
+    steps = 16
+    target = oracle_C(target_setup(w), steps)
+    sim = lbm3.Simulation(w, precision="f64", adjoint=True)
+    s0 = sim.get_state()
+    p = rollout.params_of([w]).requires_grad_(True)
+    rho = rollout.rollout(p, sim, steps, s0, 6)
+    C = rollout.phase_fields(rho, [w])[0]
+    fl = torch.as_tensor(w.solid == 0, device=C.device)
+    tg = torch.as_tensor(target, device=C.device)
+    (((C - tg) ** 2) * fl).sum().backward()
+    g_ref = p.grad.clone()
+    p2 = rollout.params_of([w]).requires_grad_(True)
+    L = rollout.rollout_loss(p2, sim, steps, s0, tg.reshape(-1), 6)
+    (2.5 * L.sum()).backward()
+    err = (p2.grad / 2.5 - g_ref).abs().max() / g_ref.abs().max()
+    print(f"rollout_loss vs rollout gradient: rel err {float(err):.3e}", flush=True)
+    assert float(err) <= 1e-12
+    sim.close()
+
+
+def test_rollout_backward_uses_its_own_parameters():
+    """Two rollouts at different parameters on one Simulation, then the first one's backward:
+    its gradient equals that of a rollout at those parameters alone, the Simulation keeps the
+    parameters it was last given, and the gradient comes back on the parameters' device."""
+    torch, lbm3, rollout = _mods()
+    w = small_cases()["walls_circle"]
+    steps = 12
+    target = torch.as_tensor(oracle_C(target_setup(w), steps))
+    fl = torch.as_tensor(w.solid == 0)
+    sim = lbm3.Simulation(w, precision="f64", adjoint=True)
+    s0 = sim.get_state()
+
+    def loss(rho):
+        C = rollout.phase_fields(rho, [w])[0]
+        return (((C - target.to(C.device)) ** 2) * fl.to(C.device)).sum()
+
+    pa = rollout.params_of([w]).to(sim.device).requires_grad_(True)
+    loss(rollout.rollout(pa, sim, steps, s0, 5)).backward()
+    g_alone = pa.grad.clone()
+    assert pa.grad.device == pa.device
+    p1 = rollout.params_of([w]).to(sim.device).requires_grad_(True)
+    p2 = (rollout.params_of([w]) + torch.tensor([[4.0, -3.0, 0.0, 0.0, 0.0]], dtype=torch.float64)).to(sim.device)
+    rho1 = rollout.rollout(p1, sim, steps, s0, 5)
+    rollout.rollout(p2.requires_grad_(True), sim, steps, s0, 5)
+    loss(rho1).backward()
+    err = (p1.grad - g_alone).abs().max() / g_alone.abs().max()
+    print(f"gradient after an interleaved rollout: rel err {float(err):.3e}", flush=True)
+    assert float(err) <= 1e-12  # (the adjoint's float atomics may reorder sums)
+    np.testing.assert_array_equal(sim.params[0], p2.detach().cpu().numpy()[0])
+    sim.close()

@@ -1,0 +1,47 @@
+"""C-ABI behaviour on the GPU that is not arithmetic: the autotuner's JSON cache."""
+import json
+
+import pytest
+
+from paper_2102_04709_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _mods():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2102_04709_amd import lbm3
+    lbm3.library()
+    return torch, lbm3
+
+
+def test_tune_cache_round_trip(tmp_path):
+    """The first autotune times the candidates and stores its pick; a second context with the same
+    shapes and precision takes the stored pick without running a step; another workload adds an
+    entry."""
+    torch, lbm3 = _mods()
+    path = str(tmp_path / "tune.json")
+    w = W.random_mixture(160, 96, seed=3, walls=True, circles=[(80.2, 47.9, 12.0)])
+    print("tune cache: first autotune (timed)", flush=True)
+    s1 = lbm3.Simulation(w, precision="f32", kernel="auto", tune_cache=path)
+    c1 = s1.autotune(3)
+    assert s1.query(7) > 0  # the candidates' warm-up steps advanced the state
+    data = json.load(open(path))
+    assert len(data) == 1
+    (key, entry), = data.items()
+    assert "f32" in key and "domains=1" in key
+    assert (entry["kernel"], entry["tile_x"], entry["tile_y"]) == c1
+    s1.close()
+    print("tune cache: second autotune (cached)", flush=True)
+    s2 = lbm3.Simulation(w, precision="f32", kernel="auto", tune_cache=path)
+    c2 = s2.autotune(3)
+    assert c2 == c1 and s2.query(7) == 0
+    assert (s2.query(8), s2.query(4), s2.query(5)) == c1
+    s2.close()
+    s3 = lbm3.Simulation(W.random_mixture(96, 64, seed=4, walls=True), precision="f32", kernel="auto",
+                         tune_cache=path)
+    s3.autotune(2)
+    s3.close()
+    assert len(json.load(open(path))) == 2
