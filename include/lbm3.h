@@ -154,6 +154,17 @@ lbm3_status lbm3_fields(lbm3_ctx *c, int32_t domain, void *dev_rho, void *dev_u,
  * every domain: host_out[3*n].  Synchronises.  Returns LBM3_ENUMERIC if a NaN/Inf was found. */
 lbm3_status lbm3_mass(lbm3_ctx *c, double *host_out);
 
+/* For callers that cannot allocate device memory or synchronise (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc): the masses of lbm3_mass, bit for bit, written
+ * asynchronously into the caller's device buffer dev_out[3*n] (FP64), allocating nothing.  The
+ * reduction's partial sums live in a fixed device array of the library, 3 * 65536 doubles
+ * (1.5 MiB) per GPU, held until the process ends; a context with more than 65536 chunks of 16
+ * rows (the sum over its domains of ceil(ny / 16)) gets LBM3_EINVAL.  Every call on one GPU, from
+ * any context or stream, shares that array: calls that overlap in time on one GPU race, so
+ * serialise them (e.g. one stream).  A NaN/Inf density shows as a non-finite sum (there is no
+ * LBM3_ENUMERIC here).  No memset is enqueued, so the call can be captured into a hipGraph. */
+lbm3_status lbm3_mass_device(lbm3_ctx *c, double *dev_out);
+
 /* Checkpointing of the whole state (all domains; the compact state of Eq. 13 and 16): a
  * device-to-device copy of the raw state planes, lbm3_state_bytes long, into / from a caller
  * buffer.  set_state(get_state(s)) continues bit-identically.  Asynchronous. */

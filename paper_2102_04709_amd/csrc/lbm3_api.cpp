@@ -470,6 +470,7 @@ bool plan(const lbm3_domain *d, int n, const lbm3_options *o, std::vector<DomHos
 struct lbm3_ctx {
   int n = 0;
   int device = 0;               // the GPU current at creation
+  double *mass_scratch = nullptr;  // that GPU's fixed scratch of lbm3_mass_device
   std::string tune_cache;       // lbm3_options.tune_cache ("" = none)
   int precision = 0;
   hipStream_t stream = nullptr;
@@ -996,6 +997,8 @@ lbm3_status lbm3_create(const lbm3_domain *d, int32_t n, const lbm3_options *o, 
   if (e != hipSuccess) return bail(hip_fail(c, e, "hipFuncSetAttribute"));
   e = hipGetDevice(&c->device);
   if (e != hipSuccess) return bail(hip_fail(c, e, "hipGetDevice"));
+  e = mass_scratch_init(c->device, &c->mass_scratch);  // once per device, with it current
+  if (e != hipSuccess) return bail(hip_fail(c, e, "hipGetSymbolAddress(scratch)"));
   if (o->tune_cache) c->tune_cache = o->tune_cache;
   e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
   if (e != hipSuccess) return bail(hip_fail(c, e, "hipStreamCreateWithFlags"));
@@ -1163,6 +1166,27 @@ lbm3_status lbm3_mass(lbm3_ctx *c, double *host_out) {
   if (bad) {
     c->err = "non-finite partial density found";
     return LBM3_ENUMERIC;
+  }
+  return LBM3_OK;
+}
+
+lbm3_status lbm3_mass_device(lbm3_ctx *c, double *dev_out) {
+  if (!c || !dev_out) return LBM3_EINVAL;
+  if (c->L.n_chunks > kMassScratchChunks) {
+    char b[200];
+    snprintf(b, sizeof b, "lbm3_mass_device: %d row chunks exceed the fixed scratch of %d (sum over domains of "
+             "ceil(ny / 16)); use lbm3_mass", c->L.n_chunks, kMassScratchChunks);
+    c->err = b;
+    return LBM3_EINVAL;
+  }
+  if (c->precision == LBM3_F64) {
+    MassArgs<double> a{c->at<DomainDev>(c->L.off_doms), c->at<uint8_t>(c->L.off_flags), c->at<double>(c->L.off_R[c->cur]),
+                       c->at<int>(c->L.off_chunk_dom), c->at<int>(c->L.off_chunk_first), c->mass_scratch, nullptr};
+    HIPC(c, launch_mass<double>(a, c->L.n_chunks, c->n, dev_out, c->stream));
+  } else {
+    MassArgs<float> a{c->at<DomainDev>(c->L.off_doms), c->at<uint8_t>(c->L.off_flags), c->at<float>(c->L.off_R[c->cur]),
+                      c->at<int>(c->L.off_chunk_dom), c->at<int>(c->L.off_chunk_first), c->mass_scratch, nullptr};
+    HIPC(c, launch_mass<float>(a, c->L.n_chunks, c->n, dev_out, c->stream));
   }
   return LBM3_OK;
 }

@@ -59,8 +59,15 @@ struct MassArgs {
   const int *chunk_dom;    // [n_chunks]
   const int *chunk_first;  // [n_dom + 1]
   double *partial;         // [3 * n_chunks]
-  int *bad;
+  int *bad;                // set to 1 on a non-finite density (may be null)
 };
+
+// Chunks (16 rows of one domain each) the fixed scratch of lbm3_mass_device holds: 3 doubles
+// each, 1.5 MiB per GPU.
+constexpr int kMassScratchChunks = 65536;
+// Device address of that scratch on `device`, which must be the current device on the first call
+// for it (the address is looked up once per device and kept).
+hipError_t mass_scratch_init(int device, double **out);
 
 enum { MODE_TILE = 0, MODE_STRIP128 = 1, MODE_STRIP256 = 2, MODE_TILE512 = 3 };
 inline bool is_tile_mode(int mode) { return mode == MODE_TILE || mode == MODE_TILE512; }

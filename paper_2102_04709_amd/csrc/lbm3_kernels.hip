@@ -24,6 +24,8 @@
 #include "lbm3_adjoint.h"
 #include "lbm3_kernels.h"
 
+#include <mutex>
+
 namespace lbm3 {
 
 // Wetting-fill kernel: four lanes per fill node, kFillNodes nodes of one domain per work-group
@@ -546,7 +548,7 @@ __global__ __launch_bounds__(kThreads) void mass_partial(MassArgs<T> A) {
       }
     }
   for (int k = 0; k < 3; ++k) red[k][threadIdx.x] = s[k];
-  if (bad) A.bad[0] = 1;
+  if (bad && A.bad) A.bad[0] = 1;
   __syncthreads();
   for (int w = kThreads / 2; w > 0; w >>= 1) {
     if (threadIdx.x < w)
@@ -653,6 +655,28 @@ hipError_t launch_mass(const MassArgs<T> &a, int n_chunks, int n_dom, double *ou
   hipLaunchKernelGGL(mass_partial<T>, dim3(n_chunks), dim3(kThreads), 0, s, a);
   hipLaunchKernelGGL(mass_final, dim3((3 * n_dom + 63) / 64), dim3(64), 0, s, a.partial, a.chunk_first, n_dom, out);
   return hipGetLastError();
+}
+
+// Partial sums of the mass reduction for lbm3_mass_device, the entry point that allocates
+// nothing: a fixed array of the library, one copy per GPU (at its own address there), shared by
+// every call on that GPU and kept until the process ends.  Host code reaches it only through the
+// device address hipGetSymbolAddress gives with that GPU current.
+static __device__ __align__(256) double scratch[3 * kMassScratchChunks];
+
+hipError_t mass_scratch_init(int device, double **out) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static double *ptr[kMaxDevices] = {};
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!ptr[device]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    ptr[device] = static_cast<double *>(p);
+  }
+  *out = ptr[device];
+  return hipSuccess;
 }
 
 size_t step_smem_bytes(int precision, int mode, int tx, int ty) {

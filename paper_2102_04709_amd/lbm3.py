@@ -27,7 +27,7 @@ ABI_SYMBOLS = [
     "lbm3_state_bytes", "lbm3_get_state", "lbm3_set_state", "lbm3_kernel_times", "lbm3_autotune",
     "lbm3_query", "lbm3_last_error", "lbm3_plan_error", "lbm3_status_string", "lbm3_destroy",
     "lbm3_set_params", "lbm3_adjoint_seed", "lbm3_adjoint_step", "lbm3_adjoint_grad",
-    "lbm3_loss_seed",
+    "lbm3_loss_seed", "lbm3_mass_device",
 ]
 
 
@@ -94,6 +94,7 @@ def library() -> C.CDLL:
             "lbm3_adjoint_step": (i32, [vp, vp, vp, vp]),
             "lbm3_adjoint_grad": (i32, [vp, dp]),
             "lbm3_loss_seed": (i32, [vp, vp, vp, vp]),
+            "lbm3_mass_device": (i32, [vp, vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -179,6 +180,10 @@ def lbm3_mass(ctx, n_domains: int) -> np.ndarray:
     out = np.zeros(3 * n_domains)
     _check(library().lbm3_mass(ctx, out.ctypes.data_as(C.POINTER(C.c_double))), ctx)
     return out.reshape(n_domains, 3)
+
+
+def lbm3_mass_device(ctx, out_ptr: int) -> None:
+    _check(library().lbm3_mass_device(ctx, C.c_void_p(out_ptr)), ctx)
 
 
 def lbm3_state_bytes(ctx) -> int:
@@ -297,6 +302,15 @@ class Simulation:
 
     def mass(self) -> np.ndarray:
         return lbm3_mass(self.ctx, self.n)
+
+    def mass_device(self, out=None):
+        """The masses of mass() into a device tensor [n, 3] (FP64), asynchronously, through the
+        entry point that allocates nothing."""
+        import torch
+        buf = torch.empty((self.n, 3), dtype=torch.float64, device=self.device) if out is None else out
+        assert buf.numel() == 3 * self.n and buf.is_contiguous() and buf.dtype == torch.float64
+        lbm3_mass_device(self.ctx, buf.data_ptr())
+        return buf
 
     def get_state(self, out=None):
         import torch
