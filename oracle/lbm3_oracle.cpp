@@ -19,9 +19,10 @@
 //                            and pressure outlet (III D)
 // Where the paper is silent or ambiguous, the choice made is marked "reading:" below.
 // Parity status: every stage is pinned by a CPU test (tests/test_oracle_*.py) against closed
-// forms, invariants, brute force (the characteristic-line march) or physics.  Parity unpinned:
-// the numerical constants of the readings -- the |G| threshold of the normals, the 1e-9 node
-// tolerance, the t = 24 end and the fallbacks of the line march -- which the physics pins
+// forms, invariants, brute force (the characteristic-line march and its fallbacks) or physics
+// (Table I angles, the Neumann triangle, Eq. 23 on a cylinder, Laplace, Poiseuille, Zou-He).
+// Parity unpinned: the numerical constants of the readings -- the |G| threshold of the normals,
+// the 1e-9 node tolerance and the t = 24 end of the line march -- which the physics pins
 // constrain only through the contact angles they produce.
 
 #include <algorithm>
@@ -450,7 +451,8 @@ bool Oracle::setup(const orc_domain *d) {
   }
 
   // Link fractions q for solid links (reading: Bouzidi linear interpolated bounce-back on the
-  // exact circles; links whose solid node lies in no circle use q = 1/2, halfway bounce-back).
+  // exact circles, applied to the total distribution; links whose solid node lies in no circle use
+  // q = 1/2, halfway bounce-back).
   qv.assign(9 * NE, 0.5);
   for (int j = 0; j < ny; ++j)
     for (int i = 0; i < nx; ++i) {
@@ -759,20 +761,28 @@ void Oracle::collide_recolour_stream() {
         }
         continue;
       }
-      // The link x -> x - e_a ends in a solid node.
+      // The link x -> x - e_a ends in a solid node.  Reading: the flow condition on curved solids
+      // (Bouzidi linear interpolated bounce-back) acts on the total distribution; each fluid's
+      // reflected population is its halfway-reflected recoloured population plus its share C_k(x)
+      // of the interpolation's change of the total, i.e. Eq. (13) applied at x to the
+      // interpolated total.  (Interpolating each fluid's populations instead mixes in the
+      // composition of the neighbour and the segregation term of the other direction, which
+      // moves the contact line on curved walls off the prescribed angles.)
       double q = qv[a * NE + e];
       int ab = OPP[a];
       int nf = ext(i + EX[a], j + EY[a]);
-      for (int k = 0; k < 3; ++k) {
-        double v;
-        if (q < 0.5 && type[nf] == T_FLUID)
-          v = 2.0 * q * fpp[(k * 9 + ab) * NE + e] + (1.0 - 2.0 * q) * fpp[(k * 9 + ab) * NE + nf];
-        else if (q < 0.5)
-          v = fpp[(k * 9 + ab) * NE + e];
-        else
-          v = (1.0 / (2.0 * q)) * fpp[(k * 9 + ab) * NE + e] + (1.0 - 1.0 / (2.0 * q)) * fpp[(k * 9 + a) * NE + e];
-        fnew[(k * 9 + a) * NE + e] = v;
-      }
+      auto total = [&](int dir, int node) {
+        return fpp[dir * NE + node] + fpp[(9 + dir) * NE + node] + fpp[(18 + dir) * NE + node];
+      };
+      double v;
+      if (q < 0.5 && type[nf] == T_FLUID)
+        v = 2.0 * q * total(ab, e) + (1.0 - 2.0 * q) * total(ab, nf);
+      else if (q < 0.5)
+        v = total(ab, e);
+      else
+        v = (1.0 / (2.0 * q)) * total(ab, e) + (1.0 - 1.0 / (2.0 * q)) * total(a, e);
+      const double dv = v - total(ab, e);
+      for (int k = 0; k < 3; ++k) fnew[(k * 9 + a) * NE + e] = fpp[(k * 9 + ab) * NE + e] + C[k * NE + e] * dv;
     }
     if (bcx == 2 && (i == 0 || i == nx - 1)) {
       // Zou-He non-equilibrium bounce-back on the total distribution (Sec. III D).

@@ -158,9 +158,32 @@ __device__ __forceinline__ T zh_add(const DomainDev &D, bool inlet, int d, const
 //   - x itself, for each of its own solid links (halfway or interpolated bounce-back).
 // No atomics: every adjoint of x's data is written by x's thread, which then applies the
 // collision transpose to them at once (adj_node).
+// Post-collision shifted population f'_dir of the fluid node (i, j) (mapped), recomputed from the
+// forward state and intermediates with the forward's own collision (bit-identical to the value
+// the forward step formed): the interpolated bounce-back of a neighbour reads it.
 template <typename S, typename T>
-__device__ __forceinline__ void stream_gather(const AdjArgs<S, T> &A, const DomainDev &D, int i, int j, int64_t tplane,
-                                              const T fp[9], const T (*sL)[kAdjN1], T lP[13], T lC[3]) {
+__device__ __noinline__ T nb_post_collision(const AdjArgs<S, T> &A, const DomainDev &D, const KT<T> &K, int i, int j,
+                                            int dir) {
+  cmap(D, i, j);
+  const int64_t li = plane_index(i, j, D.pitch), q = aidx(D, i, j), AP = A.aplane;
+  T f[9], fd[9], ux, uy;
+#pragma unroll
+  for (int a = 0; a < 9; ++a) f[a] = load_s<S, T>(A.fin + 9 * D.base + a * D.plane + li);
+  const T rt = A.X[(AX_C + 3) * AP + q];
+  T Fx = A.X[AX_F * AP + q], Fy = A.X[(AX_F + 1) * AP + q];
+  collide_shifted(f, Fx, Fy, A.X[AX_C * AP + q] * rt, A.X[(AX_C + 1) * AP + q] * rt, A.X[(AX_C + 2) * AP + q] * rt, K,
+                  fd, ux, uy);
+  T r = fd[0];
+#pragma unroll
+  for (int a = 1; a < 9; ++a)
+    if (a == dir) r = fd[a];
+  return r;
+}
+
+template <typename S, typename T>
+__device__ __forceinline__ void stream_gather(const AdjArgs<S, T> &A, const DomainDev &D, const KT<T> &K, int i, int j,
+                                              int64_t tplane, const T fp[9], const T (*sL)[kAdjN1], T lP[13],
+                                              T lC[3]) {
   // sL[c][p]: lambda_{t+1} (9 distributions, 3 densities) of the node read at tile position p of the
   // ring-1 block; the node itself is at p0
   const int p0 = (int)(threadIdx.x & (kAdjTX - 1)) + 1 + ((int)(threadIdx.x / kAdjTX) + 1) * kAdjW1;
@@ -219,9 +242,16 @@ __device__ __forceinline__ void stream_gather(const AdjArgs<S, T> &A, const Doma
     else take(d, T(1), lfv, m0, m1, m2);
     if (d != 0 && ((lk >> (9 + d)) & 1) && D.n_ibb > 0) {
       if ((lk >> (18 + d)) & 1) {
+        // y's link opposite to d is cut with the fluid node x behind it: y's interpolated total
+        // reads f'_d(x) with weight 1 - 2q, and each fluid of y takes its share C_k(y) of it
         const int a = lat_opp(d);
         const T qa = (T)A.ibb[A.ibb_of[D.base + yli]].q[a - 1];
-        if (qa < T(0.5)) take(d, T(1) - T(2) * qa, sL[a][py], m0, m1, m2);
+        if (qa < T(0.5)) {
+          const int64_t yq = aidx(D, yi, yj);
+          const T gy = sL[a][py] + m0 * A.X[AX_C * AP + yq] + m1 * A.X[(AX_C + 1) * AP + yq] +
+                       m2 * A.X[(AX_C + 2) * AP + yq];
+          lP[d] += (T(1) - T(2) * qa) * gy;
+        }
       }
     }
   }
@@ -236,15 +266,38 @@ __device__ __forceinline__ void stream_gather(const AdjArgs<S, T> &A, const Doma
     const int ab = lat_opp(a);
     if (!((lk >> ab) & 1)) continue;  // the node read at x - e_a is fluid
     const T qd = ib ? (T)ib->q[a - 1] : T(0.5);
-    const T lfa = sL[a][p0];
+    // forward: f_a(x) = v (the interpolated total), rho_k(x) += [C_k (f'_ab + w) + w R_k.e_ab] +
+    // C_k (v - f'_ab): v's adjoint gathers lambda_fa + sum_k mu_k C_k, C_k's gathers mu_k (v + w),
+    // R's the halfway term's
+    const T g = sL[a][p0] + mu0 * C[0] + mu1 * C[1] + mu2 * C[2];
+    T v;
     if (qd < T(0.5) && !((lk >> a) & 1)) {
-      take(ab, T(2) * qd, lfa, mu0, mu1, mu2);  // the neighbour's share is gathered there
+      const T c1 = T(2) * qd, c2 = T(1) - T(2) * qd;
+      v = c1 * fp[ab] + c2 * nb_post_collision(A, D, K, i + ex, j + ey, ab);
+      lP[ab] += c1 * g;  // (the neighbour's share is gathered there)
     } else if (qd < T(0.5)) {
-      take(ab, T(1), lfa, mu0, mu1, mu2);
+      v = fp[ab];
+      lP[ab] += g;
     } else {
       const T c1 = rcp(T(2) * qd), c2 = T(1) - c1;
-      take(ab, c1, lfa, mu0, mu1, mu2);
-      if (c2 != T(0)) take(a, c2, lfa, mu0, mu1, mu2);
+      v = c1 * fp[ab] + c2 * fp[a];
+      lP[ab] += c1 * g;
+      lP[a] += c2 * g;
+    }
+    const T w = wgt<T>(ab);
+    const T vw = v + w;
+    lC[0] += mu0 * vw;
+    lC[1] += mu1 * vw;
+    lC[2] += mu2 * vw;
+    const T ra_ = w * (mu0 - mu2), rb_ = w * (mu1 - mu2);
+    const int bx = lat_ex(ab), by = lat_ey(ab);
+    if (bx) {
+      lP[9] += ra_ * T(bx);
+      lP[11] += rb_ * T(bx);
+    }
+    if (by) {
+      lP[10] += ra_ * T(by);
+      lP[12] += rb_ * T(by);
     }
   }
   if (zh && i == D.nx - 1) {
@@ -456,7 +509,7 @@ __global__ __launch_bounds__(kThreads) void adj_node(AdjArgs<S, T> A, int64_t tp
         collide_shifted(f, Fx, Fy, C[0] * rt, C[1] * rt, C[2] * rt, K, fd, ux, uy);
       }
       T lP[13], lCs[3];
-      stream_gather(A, D, i, j, tplane, fd, sL, lP, lCs);
+      stream_gather(A, D, K, i, j, tplane, fd, sL, lP, lCs);
 #pragma unroll
       for (int c = 0; c < 6; ++c) nrm[c] = A.X[(AX_N + c) * AP + q];
       T lf[9], lFx, lFy, lC[3], lrt, ln[6], lgX[3];

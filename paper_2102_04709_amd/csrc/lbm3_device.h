@@ -419,32 +419,29 @@ __device__ __forceinline__ void stream_node(const Acc &acc, int gx, const Domain
       else { ra += c[0]; rb += c[1]; rc += c[2]; }
     } else {
       // the link x -> x - e_a ends in a solid node: bounce-back of the populations leaving x
-      // along -e_a (direction ab)
+      // along -e_a (direction ab).  The interpolated bounce-back acts on the total; each fluid
+      // takes its halfway-reflected recoloured population plus its share C_k(x) of the
+      // interpolation's change of the total (Eq. 13 at x applied to the interpolated total).
       const int ab = lat_opp(a);
       const T qd = ib ? (T)ib->q[a - 1] : T(0.5);
       const T fab = acc.f(ab, 0, 0);
       T own_ab[3];
       fluid_parts<T>(acc, 0, 0, ab, own_ab);
+      T v;
       if (qd < T(0.5) && !acc.solid(ex, ey)) {
-        T nb_ab[3];
-        fluid_parts<T>(acc, ex, ey, ab, nb_ab);
         const T c1 = T(2) * qd, c2 = T(1) - T(2) * qd;
-        fo[a] = c1 * fab + c2 * acc.f(ab, ex, ey);
-        ra += c1 * own_ab[0] + c2 * nb_ab[0];
-        rb += c1 * own_ab[1] + c2 * nb_ab[1];
-        rc += c1 * own_ab[2] + c2 * nb_ab[2];
+        v = c1 * fab + c2 * acc.f(ab, ex, ey);
       } else if (qd < T(0.5)) {
-        fo[a] = fab;
-        ra += own_ab[0]; rb += own_ab[1]; rc += own_ab[2];
+        v = fab;
       } else {
-        T own_a[3];
-        fluid_parts<T>(acc, 0, 0, a, own_a);
         const T c1 = rcp(T(2) * qd), c2 = T(1) - c1;
-        fo[a] = c1 * fab + c2 * acc.f(a, 0, 0);
-        ra += c1 * own_ab[0] + c2 * own_a[0];
-        rb += c1 * own_ab[1] + c2 * own_a[1];
-        rc += c1 * own_ab[2] + c2 * own_a[2];
+        v = c1 * fab + c2 * acc.f(a, 0, 0);
       }
+      fo[a] = v;
+      const T dv = v - fab;  // zero at q = 1/2: halfway bounce-back exactly
+      ra += own_ab[0] + acc.C(0, 0, 0) * dv;
+      rb += own_ab[1] + acc.C(1, 0, 0) * dv;
+      rc += own_ab[2] + acc.C(2, 0, 0) * dv;
     }
   }
   if (D.bcx == BCX_ZOUHE && (gx == 0 || gx == D.nx - 1)) {

@@ -104,6 +104,58 @@ def flat_janus(nx=120, ny=60, R=20.0, theta=(60.0, 120.0), sigma=(0.01, 0.01, 0.
                     solid, _phases([m1, m2], solid))
 
 
+# Table I of Sec. III A: (theta_rg, theta_br, theta_gb) in degrees, theta_kl measured inside fluid k.
+TABLE1 = {"a": (90.0, 60.0, 120.0), "b": (60.0, 90.0, 120.0), "c": (120.0, 60.0, 90.0),
+          "d": (60.0, 120.0, 90.0), "e": (90.0, 90.0, 90.0), "f": (90.0, 120.0, 60.0)}
+
+
+def janus_flat_table1(case="c", scale=1.0, R=None) -> Workload:
+    """Sec. III A with the paper's labels (red -> fluid 1, green -> fluid 2, blue -> fluid 3): a
+    semicircular Janus droplet of radius 80 s (red left half, blue right half) resting on the wall
+    surface y = 0.5 at the centre of a (320 s) x (180 s) domain, surrounded by green; walls are the
+    solid rows 0 and ny-1, periodic in x; viscosities 0.1, tensions 0.01.  Table I's angles enter
+    as theta13 = theta_rb = 180 - theta_br and theta23 = theta_gb (theta12 = theta_rg follows from
+    Eq. 18).  R overrides the radius (Fig. 3's resolution series keeps the domain 4 R x 2.25 R)."""
+    rg, br, gb = TABLE1[case]
+    if R is None:
+        R = 80.0 * scale
+    nx, ny = int(round(4.0 * R)), int(round(2.25 * R))
+    x, y = _grid(nx, ny)
+    solid = _walls(nx, ny)
+    d = _disk(x, y, nx / 2.0, 0.5, R)
+    fl = solid == 0
+    rho = np.zeros((3, ny, nx))
+    rho[0][d & (x < nx / 2.0) & fl] = 1.0
+    rho[2][d & (x >= nx / 2.0) & fl] = 1.0
+    rho[1][~d & fl] = 1.0
+    return Workload(f"table1_{case}_R{R:g}", nx, ny, 0, BC_PERIODIC, (0.1, 0.1, 0.1), (0.01, 0.01, 0.01),
+                    (180.0 - br, gb), solid, rho)
+
+
+def janus_cylinder(theta=90.0, scale=1.0) -> Workload:
+    """Sec. III B with the paper's labels (red -> 1, green -> 2, blue -> 3): a perfect Janus droplet
+    (red left, blue right; the negligible red-blue tension taken as 1e-4) on a cylinder of radius
+    40 s centred at (100 s, 60 s) in a (200 s) x (200 s) domain, surrounded by green; walls are the
+    solid rows 0 and ny-1, periodic in x; viscosities 0.1, sigma_rg = sigma_gb = 0.01 and
+    theta_rg = theta_bg = theta.  With sigma_rb -> 0, Eq. (18) leaves theta_br = 90, so the inputs
+    are theta13 = theta_rb = 90 and theta23 = theta_gb = 180 - theta (theta12 = theta_rg = theta).
+    The droplet starts as a disk of radius 45 s centred 66 s above the cylinder's centre (the
+    paper does not give the start; the equilibrium radius R_j and distance D_sj are measured)."""
+    nx = ny = int(round(200 * scale))
+    Rs, Rj = 40.0 * scale, 45.0 * scale
+    cx, cy, D0 = 100.0 * scale, 60.0 * scale, 66.0 * scale
+    x, y = _grid(nx, ny)
+    solid = _walls(nx, ny) | _solid_disk(x, y, cx, cy, Rs).astype(np.uint8)
+    fl = solid == 0
+    d = _disk(x, y, cx, cy + D0, Rj) & fl
+    rho = np.zeros((3, ny, nx))
+    rho[0][d & (x < cx)] = 1.0
+    rho[2][d & (x >= cx)] = 1.0
+    rho[1][~d & fl] = 1.0
+    return Workload(f"janus_cylinder_{theta:g}_s{scale:g}", nx, ny, 0, BC_PERIODIC, (0.1, 0.1, 0.1),
+                    (0.01, 1e-4, 0.01), (90.0, 180.0 - theta), solid, rho, circles=np.array([[cx, cy, Rs]]))
+
+
 # ---- Sec. III B: Janus droplet on a cylinder ---------------------------------------------
 
 def cylinder_janus(nx=400, ny=400, Rs=60.0, Rj=50.0, centre=None, theta=(90.0, 90.0),
