@@ -88,22 +88,37 @@ def roofline(sim, launches=50, traffic=None):
             "ms_per_launch": round(ms_step, 5), "fill_kernel_ms_per_launch": round(ms_fill, 5)}
 
 
-def measure(workloads_, precision, steps, warmup, graph=100, config=None):
+def graph_block_for(steps, preferred):
+    """Steps per captured graph: the preferred block, or less so that the timed steps replay at
+    least two graphs (lbm3_step replays a graph only for whole blocks)."""
+    if preferred <= 0:
+        return 0
+    return max(2, min(preferred, (steps // 2) // 2 * 2))
+
+
+def measure(workloads_, precision, steps, warmup, graph=100, config=None, persistent=0):
     """config = (kernel, tile_x, tile_y) as lbm3_autotune returns it; None runs the autotuner."""
     from paper_2102_04709_amd import lbm3
+    graph = graph_block_for(steps, graph)
     if config is None:
-        sim = lbm3.Simulation(workloads_, precision=precision, graph_block_steps=graph)
+        sim = lbm3.Simulation(workloads_, precision=precision, graph_block_steps=graph,
+                              persistent_blocks=persistent)
         tile = sim.autotune(20)  # 20 launches per candidate: a stable pick between close configurations
     else:
         k, tx, ty = config
         sim = lbm3.Simulation(workloads_, precision=precision, graph_block_steps=graph, kernel=int(k),
-                              tile=(tx, ty) if k in (0, 3) else (0, ty))
+                              tile=(tx, ty) if k in (0, 3) else (0, ty), persistent_blocks=persistent)
         tile = tuple(config)
-    dt = timed_run(sim, steps, warmup)
+    sim.step(warmup)
+    g0 = sim.query(9)
+    dt = timed_run(sim, steps, 0)
+    replays = int(sim.query(9) - g0)
     nodes = sim.query(1)
     traffic = traffic_for(workloads_[0], precision, tile) if len(workloads_) == 1 else None
     res = {"mlups": round(nodes * steps / dt / 1e6, 1), "ms_per_step": round(dt / steps * 1e3, 5),
-           "tile": list(tile) if tile else None, "roofline": roofline(sim, traffic=traffic)}
+           "tile": list(tile) if tile else None, "graph_block_steps": graph,
+           "graph_replays_timed": replays, "steps_in_graphs": replays * graph,
+           "persistent_blocks": persistent, "roofline": roofline(sim, traffic=traffic)}
     sim.close()
     return res, dt
 
@@ -165,22 +180,69 @@ def measure_adjoint(w, precision, steps=40, rollout_steps=400, every=100):
     return res
 
 
-def cpu_baseline(w, budget_s=20.0):
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_rate(w, steps, threads):
     from oracle import pyoracle as po
-    threads = po.max_threads()
     po.set_threads(threads)
     o = po.Oracle(w)
-    o.step(2)  # warm-up: thread pool start and first touch of the arrays
+    o.step(1)  # untimed: thread pool start and first touch of the arrays
     t0 = time.perf_counter()
-    o.step(10)
-    per = (time.perf_counter() - t0) / 10
-    n = max(1, min(20000, int(budget_s / max(per, 1e-6))))
-    t0 = time.perf_counter()
-    o.step(n)
+    o.step(steps)
     dt = time.perf_counter() - t0
-    return {"value": round(w.nodes * n / dt / 1e6, 3), "unit": "MLUPS", "cores": threads,
-            "kind": "oracle",
-            "sample": f"{w.name} {w.nx}x{w.ny}, FP64 oracle, {n} steps after 12 untimed steps, {dt:.1f} s"}
+    return w.nodes * steps / dt / 1e6, dt
+
+
+def cpu_baseline(w, budget_s=20.0, full=True):
+    """The FP64 oracle (plain, untuned) on the host cores.  The headline value is its MLUPS on the
+    headline workload with all threads, on a bounded sample; with full=True the line also carries
+    the per-configuration samples of the baseline plan at 1 thread and at all threads (steps cut so
+    the whole leg stays within about a minute) and the wall time of the adjoint's finite-difference
+    set extrapolated from the measured inverse-problem rate."""
+    from oracle import pyoracle as po
+    from paper_2102_04709_amd import workloads as W
+    threads = po.max_threads()
+    rate0, dt0 = _oracle_rate(w, 20, threads)
+    n = max(1, min(20000, int(budget_s / max(dt0 / 20, 1e-6))))
+    rate, dt = _oracle_rate(w, n, threads)
+    out = {"value": round(rate, 3), "unit": "MLUPS", "cores": threads, "kind": "oracle",
+           "sample": f"{w.name} {w.nx}x{w.ny}, FP64 oracle, {n} steps after 1 untimed step, {dt:.1f} s",
+           "cpu_model": cpu_model(), "nproc": os.cpu_count()}
+    if not full:
+        return out
+    sweep = W.pillar_sweep()
+    by_size = sorted(sweep, key=lambda v: v.nodes)
+    plan = [("flat_janus_120x60 (full 2000 steps)", W.flat_janus(), 2000, 200),
+            ("cylinder_janus_400x400", w, 200, 10),
+            ("capillary_intrusion_1024x64 ratio 100", W.capillary_intrusion(ratio=100.0), 200, 20),
+            ("pillar sweep, smallest domain", by_size[0], 100, 10),
+            ("pillar sweep, 2nd smallest domain", by_size[1], 100, 10),
+            ("pillar sweep, 2nd largest domain", by_size[-2], 100, 5),
+            ("pillar sweep, largest domain", by_size[-1], 100, 5),
+            ("inverse problem 512x256", W.inverse_problem(), 100, 10)]
+    rows = []
+    for name, wk, steps_all, steps_one in plan:
+        r_all, t_all = _oracle_rate(wk, steps_all, threads)
+        r_one, t_one = _oracle_rate(wk, steps_one, 1)
+        rows.append({"config": name, "nodes": wk.nodes, "steps_all_threads": steps_all,
+                     "mlups_all_threads": round(r_all, 3), "steps_1_thread": steps_one,
+                     "mlups_1_thread": round(r_one, 3), "seconds": round(t_all + t_one, 2)})
+    po.set_threads(threads)
+    inv = rows[-1]
+    fd_lup = 2 * 3 * 5 * 4000 * inv["nodes"] + 2 * 4000 * inv["nodes"]
+    out["plan"] = rows
+    out["fd_set_wall_s_extrapolated"] = round(fd_lup / (inv["mlups_all_threads"] * 1e6), 1)
+    out["fd_set_note"] = ("32 oracle runs of 4000 steps (loss, target, 5 parameters x 2 signs x 3 steps h, h/2, "
+                          "h/10) at the measured all-thread rate")
+    return out
 
 
 def main():
@@ -190,6 +252,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=400)
     ap.add_argument("--skip-extra", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--cpu-quick", action="store_true", help="only the headline sample of the CPU baseline")
     ap.add_argument("--only", default=None,
                     help="run one workload (cylinder_400_f32|f64|f16, cylinder_4000_f32|f64|f16, "
                          "pillar_sweep_96_f32, adjoint_512_f32|f64, adjoint_4000_f32) and print its measurement")
@@ -245,7 +308,9 @@ def main():
         "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "cylinder_janus_400x400", "nx": 400, "ny": 400,
-                   "precision": "f32 compute, f32 shifted storage", "graph_block_steps": 100,
+                   "precision": "f32 compute, f32 shifted storage",
+                   "graph_block_steps": head["graph_block_steps"],
+                   "graph_replays_timed": head["graph_replays_timed"],
                    "tile": head["tile"], "parallelism": "1 GPU"},
         "roofline": head["roofline"],
     }
@@ -265,6 +330,12 @@ def main():
         r, _ = measure(sweep, "f32", 100, 10, graph=10)
         r["domains"] = len(sweep)
         extra["pillar_sweep_96_f32"] = r
+        log("variant: batched pillar sweep, persistent launch (one work-group loop per slot)")
+        cfg = tuple(r["tile"])
+        slots = 256 * (6 if cfg[0] == 0 else 3)  # the work-groups one round of the chip holds
+        rp, _ = measure(sweep, "f32", 100, 10, graph=10, config=cfg, persistent=slots)
+        rp["domains"] = len(sweep)
+        extra["pillar_sweep_96_f32_persistent"] = rp
         for p in ("f32", "f64"):
             log(f"variant: adjoint step, inverse problem 512x256 {p}")
             extra[f"adjoint_512_{p}"] = measure_adjoint(W.inverse_problem(), p)
@@ -274,7 +345,7 @@ def main():
         out["roofline_hbm"] = extra["cylinder_4000_f32"]["roofline"]
     if not args.skip_cpu:
         log("cpu baseline: oracle")
-        out["cpu_baseline"] = cpu_baseline(w)
+        out["cpu_baseline"] = cpu_baseline(w, full=not args.cpu_quick)
     print(json.dumps(out), flush=True)
 
 

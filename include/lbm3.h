@@ -237,7 +237,7 @@ lbm3_status lbm3_autotune(lbm3_ctx *c, int32_t steps_per_candidate, int32_t *cho
  * fused kernel (state read
  * once and written once), 1 = total nodes, 2 = fill nodes, 3 = interpolated-bounce-back nodes,
  * 4 = tile_x, 5 = tile_y, 6 = work items, 7 = steps taken, 8 = kernel (0/3 tiles of 256/512
- * threads, 1/2 strips). */
+ * threads, 1/2 strips), 9 = hipGraph replays so far, 10 = steps per replayed graph (0: none). */
 lbm3_status lbm3_query(const lbm3_ctx *c, int32_t key, double *value);
 
 /* Status text: the message of the last failure on a context (never NULL; the string lives until

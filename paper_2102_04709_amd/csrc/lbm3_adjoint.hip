@@ -188,7 +188,6 @@ __device__ __forceinline__ void stream_gather(const AdjArgs<S, T> &A, const Doma
   // ring-1 block; the node itself is at p0
   const int p0 = (int)(threadIdx.x & (kAdjTX - 1)) + 1 + ((int)(threadIdx.x / kAdjTX) + 1) * kAdjW1;
   const int64_t AP = A.aplane;
-  const int64_t P = D.plane;
   const int64_t li = plane_index(i, j, D.pitch);
   const int64_t q = aidx(D, i, j);
   const T *Lf = A.lin + 9 * D.base;

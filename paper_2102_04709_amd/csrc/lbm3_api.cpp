@@ -63,6 +63,7 @@ struct DomHost {
   DomainDev dd;
   std::vector<uint8_t> flags;   // [(ny+4) * pitch]
   std::vector<FillNode> fill;
+  std::vector<FillCand> cand;   // [fill][4 lines][kFillCands]
   std::vector<uint32_t> far;    // kFarW rows per fill node: its far fluid mask
   std::vector<IbbNode> ibb;
 };
@@ -70,7 +71,7 @@ struct DomHost {
 struct Layout {
   size_t off_F[2], off_R[2], off_flags, off_fill, off_fillC, off_ibb, off_doms, off_work, off_fwork, off_partial,
       off_chunk_dom, off_chunk_first, off_mass, off_bad, off_aX, off_awork, off_raw, off_tibb, off_fblk, off_ibbof,
-      off_links, off_far, off_lpart, off_lfirst, total;
+      off_links, off_far, off_lpart, off_lfirst, off_cand, total;
   int64_t total_plane;
   int64_t aplane;  // elements of one adjoint scratch plane (all domains' extended grids)
   int n_fill, n_ibb, n_chunks, max_work, n_fwork, n_awork, n_fblk;
@@ -154,11 +155,49 @@ void param_jacobian(const double *theta_deg, const double *sigma, double J[9][5]
   }
 }
 
+// The crossings of a fill node's four characteristic lines (fluid k = line / 2, side line % 2) for
+// the angles Eq. (21) gives when at most two fluids are present at D0: fluid 1 theta13, theta12 or
+// their mean, fluid 2 theta23, theta21 = pi - theta12 or their mean; with the fill's own angle
+// clamp, sine and cosine and march, in FP64.  flags: the domain's flag plane.
+void fill_candidates(const DomainDev &D, const uint8_t *flags, const FillNode &fn, FillCand *out) {
+  const double PI = 3.14159265358979323846;
+  const bool zh = D.bcx == BCX_ZOUHE;
+  auto fluid_at = [&](int i, int j) -> bool {
+    if (zh) {
+      if (i < 0 || i >= D.nx) return false;
+    } else {
+      i = ((i % D.nx) + D.nx) % D.nx;
+    }
+    if (D.yper) j = ((j % D.ny) + D.ny) % D.ny;
+    else if (j < 0 || j >= D.ny) return false;
+    return !(flags[plane_index(i, j, D.pitch)] & FL_SOLID);
+  };
+  auto wrapped = [&](int i, int j) {
+    if (!zh) i = ((i % D.nx) + D.nx) % D.nx;
+    if (D.yper) j = ((j % D.ny) + D.ny) % D.ny;
+    return (int32_t)plane_index(i, j, D.pitch);
+  };
+  const double th21 = PI - D.th12;
+  const double ang[2][kFillCands] = {{D.th13, D.th12, 0.5 * (D.th13 + D.th12)}, {D.th23, th21, 0.5 * (D.th23 + th21)}};
+  for (int line = 0; line < 4; ++line)
+    for (int c = 0; c < kFillCands; ++c) {
+      const double tk = std::min(std::max(ang[line >> 1][c], 5.0 * PI / 180.0), 175.0 * PI / 180.0);
+      const double phi = std::fabs(0.5 * PI - tk);
+      double sp, cp;
+      sincos_quadrant(phi, sp, cp);
+      if (line & 1) sp = -sp;
+      const double nx = fn.nx, ny = fn.ny, tx = -ny, ty = nx;
+      const LineHit h = march_line(fn.i, fn.j, cp * nx + sp * tx, cp * ny + sp * ty, fluid_at);
+      out[line * kFillCands + c] = h.ok ? FillCand{wrapped(h.i0, h.j0), wrapped(h.i1, h.j1), h.w} : FillCand{-1, -1, 0.0};
+    }
+}
+
 bool validate_and_build(const lbm3_domain &d, int dom, double beta0, DomHost &H, std::string &err) {
-  char buf[256];
+  char buf[256];  // detail of a message; fail() formats into its own buffer (never from buf into buf)
   auto fail = [&](const char *m) {
-    snprintf(buf, sizeof buf, "domain %d: %s", dom, m);
-    err = buf;
+    char out[320];
+    snprintf(out, sizeof out, "domain %d: %s", dom, m);
+    err = out;
     return false;
   };
   if (d.nx < 3 || d.ny < 3) return fail("nx and ny must be >= 3");
@@ -317,6 +356,8 @@ bool validate_and_build(const lbm3_domain &d, int dom, double beta0, DomHost &H,
         }
         H.flags[p] |= FL_FILL;
         H.fill.push_back(fn);
+        H.cand.resize(H.cand.size() + 4 * kFillCands);
+        fill_candidates(D, H.flags.data(), fn, H.cand.data() + H.cand.size() - 4 * kFillCands);
       }
   // Interpolated bounce-back link fractions.
   for (int j = 0; j < ny; ++j)
@@ -442,6 +483,7 @@ bool plan(const lbm3_domain *d, int n, const lbm3_options *o, std::vector<DomHos
   L.off_tibb = take(sizeof(TileIbb) * std::max(ni, 1));
   L.off_fblk = take(sizeof(FillBlock) * std::max(nfb, 1));
   L.off_far = take(sizeof(uint32_t) * kFarW * (size_t)std::max(nf, 1));
+  L.off_cand = take(sizeof(FillCand) * 4 * kFillCands * (size_t)std::max(nf, 1));
   L.off_ibb = take(sizeof(IbbNode) * std::max(ni, 1));
   L.off_doms = take(sizeof(DomainDev) * n);
   L.off_work = take(sizeof(WorkItem) * maxw);
@@ -499,6 +541,7 @@ struct lbm3_ctx {
   bool adjoint = false;
   hipGraphExec_t graph = nullptr;
   bool graph_valid = false;
+  long graph_launches = 0;  // hipGraph replays so far
   std::string err;
 
   template <typename P>
@@ -655,6 +698,7 @@ FillArgs<T> fill_args(lbm3_ctx *c, int which) {
   f.blocks = c->at<FillBlock>(c->L.off_fblk);
   f.n_blocks = c->L.n_fblk;
   f.far = c->at<uint32_t>(c->L.off_far);
+  f.cand = c->at<FillCand>(c->L.off_cand);
   f.doms = c->at<DomainDev>(c->L.off_doms);
   f.flags = c->at<uint8_t>(c->L.off_flags);
   f.rho = c->at<T>(c->L.off_R[which]);
@@ -1040,6 +1084,10 @@ lbm3_status lbm3_create(const lbm3_domain *d, int32_t n, const lbm3_options *o, 
     for (int i = 0; i < n; ++i) far.insert(far.end(), H[i].far.begin(), H[i].far.end());
     if (!far.empty())
       CK(hipMemcpyAsync(c->at<void>(L.off_far), far.data(), sizeof(uint32_t) * far.size(), hipMemcpyHostToDevice, s));
+    std::vector<FillCand> cand;  // candidate crossings of all fill nodes, in fill order
+    for (int i = 0; i < n; ++i) cand.insert(cand.end(), H[i].cand.begin(), H[i].cand.end());
+    if (!cand.empty())
+      CK(hipMemcpyAsync(c->at<void>(L.off_cand), cand.data(), sizeof(FillCand) * cand.size(), hipMemcpyHostToDevice, s));
     CK(hipStreamSynchronize(s));
   }
   std::vector<FillBlock> fblk;  // work-groups of the fill kernel: up to kFillNodes nodes of one domain
@@ -1118,6 +1166,7 @@ lbm3_status lbm3_step(lbm3_ctx *c, int32_t nsteps) {
     while (left >= c->graph_block) {
       HIPC(c, hipGraphLaunch(c->graph, c->stream));
       left -= c->graph_block;
+      ++c->graph_launches;
     }
   }
   lbm3_status st = enqueue_steps(c, left, c->stream);
@@ -1233,6 +1282,13 @@ lbm3_status lbm3_set_params(lbm3_ctx *c, int32_t domain, const double *theta_deg
   c->params[domain] = {{theta_deg[0], theta_deg[1]}, {sigma[0], sigma[1], sigma[2]}};
   HIPC(c, hipMemcpyAsync(c->at<DomainDev>(c->L.off_doms) + domain, &c->doms[domain], sizeof(DomainDev),
                          hipMemcpyHostToDevice, c->stream));
+  // the fill's candidate crossings follow the angles
+  std::vector<FillCand> cand(4 * kFillCands * (size_t)std::max(D.n_fill, 1));
+  for (int p = 0; p < D.n_fill; ++p)
+    fill_candidates(D, c->hflags.data() + D.base, c->hfill[D.fill_off + p], cand.data() + 4 * kFillCands * (size_t)p);
+  if (D.n_fill > 0)
+    HIPC(c, hipMemcpyAsync(c->at<FillCand>(c->L.off_cand) + 4 * kFillCands * (size_t)D.fill_off, cand.data(),
+                           sizeof(FillCand) * 4 * kFillCands * D.n_fill, hipMemcpyHostToDevice, c->stream));
   HIPC(c, hipStreamSynchronize(c->stream));
   return LBM3_OK;
 }
@@ -1420,6 +1476,8 @@ lbm3_status lbm3_query(const lbm3_ctx *c, int32_t key, double *value) {
     case 6: *value = (double)c->work.size(); break;
     case 7: *value = (double)c->steps; break;
     case 8: *value = c->mode; break;
+    case 9: *value = (double)c->graph_launches; break;
+    case 10: *value = c->graph_block; break;
     default: return LBM3_EINVAL;
   }
   return LBM3_OK;

@@ -103,10 +103,14 @@ __device__ __forceinline__ double cfrac_at(const T *r, int64_t P, int64_t q, int
 // interpolates; the lanes of a fluid then combine their values with Eq. (22) and lane 0
 // receives the second fluid's value.  Returns (C1, C2) in lane 0.  `stage` runs in every lane
 // right before the march (it places the node's far mask at `far_rows`, a work-group barrier).
+// cand (may be null): the line's crossings for the pure-composition angles of its fluid; when C at
+// D0 leaves Eq. (21) one of them (the other two fluids' weights below 1e-15 of their sum, or both
+// absent) the line takes that crossing instead of marching, and the densities at its nodes are
+// loaded together with those of D0.
 template <typename T, class Stage>
 __device__ __forceinline__ void fill_lanes(const FillNode &fn, const DomainDev &D, const uint8_t *flags,
                                            const T *r, const uint32_t *far_rows, const Stage &stage, int line,
-                                           bool active, double &c1, double &c2) {
+                                           bool active, double &c1, double &c2, const FillCand *cand = nullptr) {
   const int64_t P = D.plane;
   auto fluid_at = [&](int i, int j) -> bool {
     const int dx = i - fn.i, dy = j - fn.j;
@@ -127,6 +131,19 @@ __device__ __forceinline__ void fill_lanes(const FillNode &fn, const DomainDev &
   };
   const double PI = 3.14159265358979323846;
   const int k = line >> 1;
+  // the candidate crossings' densities, loaded beside those of D0
+  FillCand cd[kFillCands];
+  T rc[kFillCands][2][3];
+#pragma unroll
+  for (int c = 0; c < kFillCands; ++c) {
+    cd[c] = cand ? cand[c] : FillCand{-1, -1, 0.0};
+    const int64_t qa = cd[c].a >= 0 ? cd[c].a : fn.d0a, qb = cd[c].a >= 0 ? cd[c].b : fn.d0a;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      rc[c][0][q] = r[q * P + qa];
+      rc[c][1][q] = r[q * P + qb];
+    }
+  }
   // C at D0 for the weighted contact angle of Eq. (21).
   double Cb[3];
 #pragma unroll
@@ -135,24 +152,52 @@ __device__ __forceinline__ void fill_lanes(const FillNode &fn, const DomainDev &
     Cb[q] = ca + fn.d0w * (cb - ca);
   }
   double th;
+  int pick = -1;  // the candidate crossing that applies (-1: march)
   if (k == 0) {
     const double a = fmax(Cb[1], 0.0), b = fmax(Cb[2], 0.0), den = a + b;
     th = den > 1e-12 ? (b * D.th13 + a * D.th12) / den : 0.5 * (D.th13 + D.th12);
+    pick = !(den > 1e-12) ? 2 : (a <= 1e-15 * den ? 0 : (b <= 1e-15 * den ? 1 : -1));
   } else {
     const double a2 = fmax(Cb[0], 0.0), b = fmax(Cb[2], 0.0), den2 = a2 + b;
     const double th21 = PI - D.th12;
     th = den2 > 1e-12 ? (b * D.th23 + a2 * th21) / den2 : 0.5 * (D.th23 + th21);
+    pick = !(den2 > 1e-12) ? 2 : (a2 <= 1e-15 * den2 ? 0 : (b <= 1e-15 * den2 ? 1 : -1));
   }
+  if (!cand) pick = -1;
   const double tk = fmin(fmax(th, 5.0 * PI / 180.0), 175.0 * PI / 180.0);
-  const double phi = fabs(0.5 * PI - tk);
-  double sp, cp;
-  sincos_quadrant(phi, sp, cp);
-  if (line & 1) sp = -sp;
-  const double nx = fn.nx, ny = fn.ny, tx = -ny, ty = nx;
   double v = 0.0;
   int ok = 0;
   stage();
-  if (active) {
+  if (active && pick >= 0) {
+    // the precomputed crossing of this composition's angle
+    FillCand h = cd[0];
+    double ra[3], rb[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      ra[q] = (double)rc[0][0][q];
+      rb[q] = (double)rc[0][1][q];
+    }
+#pragma unroll
+    for (int c = 1; c < kFillCands; ++c)
+      if (pick == c) {
+        h = cd[c];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          ra[q] = (double)rc[c][0][q];
+          rb[q] = (double)rc[c][1][q];
+        }
+      }
+    if (h.a >= 0) {
+      const double ca = ra[k] / (ra[0] + ra[1] + ra[2]), cb = rb[k] / (rb[0] + rb[1] + rb[2]);
+      v = ca + h.w * (cb - ca);
+      ok = 1;
+    }
+  } else if (active) {
+    const double phi = fabs(0.5 * PI - tk);
+    double sp, cp;
+    sincos_quadrant(phi, sp, cp);
+    if (line & 1) sp = -sp;
+    const double nx = fn.nx, ny = fn.ny, tx = -ny, ty = nx;
     const LineHit h = march_line_masked(fn.i, fn.j, cp * nx + sp * tx, cp * ny + sp * ty, fn.mask, far_rows, fluid_at);
     if (h.ok) {
       const double ca = cfrac_at(r, P, node_q(h.i0, h.j0), k), cb = cfrac_at(r, P, node_q(h.i1, h.j1), k);
@@ -250,27 +295,28 @@ __device__ __forceinline__ bool pair_norm(double gx, double gy, double eps, doub
 // Eq. (10) stress sum over the fluid pairs 12, 13, 23 (the double sum over ordered pairs with
 // the factor 1/2 equals the sum over unordered pairs, since G_lk = -G_kl), and the pair normals
 // n_kl = G_kl / |G_kl| (zero when |G_kl| <= eps).
+// The pair term sigma A |G| (I - n n^T) is written as (sigma A / |G|) (Gy^2, -Gx Gy, Gx^2).
 template <typename T>
 __device__ __forceinline__ void pair_stress(const T cc[3], const T g[3][2], T rho, const KT<T> &K,
                                             T eps, T &txx, T &txy, T &tyy, T nrm[6]) {
   txx = txy = tyy = T(0);
   const int pk[3] = {0, 0, 1}, pl[3] = {1, 2, 2};
+  const T r[3] = {cc[0] * rho, cc[1] * rho, cc[2] * rho};
 #pragma unroll
   for (int pr = 0; pr < 3; ++pr) {
     const int k = pk[pr], l = pl[pr];
     const T Gx = cc[l] * g[k][0] - cc[k] * g[l][0];
     const T Gy = cc[l] * g[k][1] - cc[k] * g[l][1];
-    const T rk = cc[k] * rho, rl = cc[l] * rho;
-    const T Akl = fmin(fmax(T(1e6) * rk * rl, T(0)), T(1));
+    const T Akl = fmin(fmax(T(1e6) * r[k] * r[l], T(0)), T(1));
     T mag, im;
     if (pair_norm(Gx, Gy, eps, mag, im)) {
-      const T nx = Gx * im, ny = Gy * im;
-      const T coef = K.sig[pr] * Akl * mag;
-      txx += coef * (T(1) - nx * nx);
-      txy += coef * (-nx * ny);
-      tyy += coef * (T(1) - ny * ny);
-      nrm[2 * pr] = nx;
-      nrm[2 * pr + 1] = ny;
+      const T c = K.sig[pr] * Akl * im;
+      const T cx = c * Gx, cy = c * Gy;
+      txx += cy * Gy;
+      txy -= cx * Gy;
+      tyy += cx * Gx;
+      nrm[2 * pr] = Gx * im;
+      nrm[2 * pr + 1] = Gy * im;
     } else {
       nrm[2 * pr] = T(0);
       nrm[2 * pr + 1] = T(0);
@@ -293,16 +339,20 @@ __device__ __forceinline__ void div_stress(const T *xx, const T *xy, const T *yy
 template <typename T>
 __device__ __forceinline__ void collide_shifted(const T f[9], T &Fx, T &Fy, T r0, T r1, T r2,
                                                 const KT<T> &K, T fd[9], T &ux, T &uy) {
-  const T s14 = f[1] + f[2] + f[3] + f[4], s58 = f[5] + f[6] + f[7] + f[8];
+  // moments m = M f (Eq. 4) with shared partial sums
+  const T s13 = f[1] + f[3], s24 = f[2] + f[4], s57 = f[5] + f[7], s68 = f[6] + f[8];
+  const T s14 = s13 + s24, s58 = s57 + s68;
+  const T d13 = f[1] - f[3], d24 = f[2] - f[4], d58 = f[5] - f[8], d67 = f[6] - f[7];
+  const T qx = (f[5] - f[6]) - (f[7] - f[8]), qy = d58 + d67;  // f5 - f6 - f7 + f8, f5 + f6 - f7 - f8
   const T drho = f[0] + s14 + s58;
   const T m1 = -T(4) * f[0] - s14 + T(2) * s58;
   const T m2 = T(4) * f[0] - T(2) * s14 + s58;
-  const T jx = f[1] - f[3] + f[5] - f[6] - f[7] + f[8];
-  const T m4 = -T(2) * f[1] + T(2) * f[3] + f[5] - f[6] - f[7] + f[8];
-  const T jy = f[2] - f[4] + f[5] + f[6] - f[7] - f[8];
-  const T m6 = -T(2) * f[2] + T(2) * f[4] + f[5] + f[6] - f[7] - f[8];
-  const T m7 = f[1] - f[2] + f[3] - f[4];
-  const T m8 = f[5] - f[6] + f[7] - f[8];
+  const T jx = d13 + qx;
+  const T m4 = qx - T(2) * d13;
+  const T jy = d24 + qy;
+  const T m6 = qy - T(2) * d24;
+  const T m7 = s13 - s24;
+  const T m8 = s57 - s68;
   const T rho = T(1) + drho;
   Fx += rho * K.g0;
   Fy += rho * K.g1;
@@ -325,16 +375,19 @@ __device__ __forceinline__ void collide_shifted(const T f[9], T &Fx, T &Fy, T r0
   const T d6 = (s4 * (m6 + rho * uy) + h4 * Fy) * T(1.0 / 12.0);
   const T d7 = (s1 * (m7 - rho * (ux * ux - uy * uy)) - h1 * T(2) * (ux * Fx - uy * Fy)) * T(0.25);
   const T d8 = (s1 * (m8 - rho * ux * uy) - h1 * (ux * Fy + uy * Fx)) * T(0.25);
-  // f' = f - M^T d
-  fd[0] = f[0] - (-T(4) * d1 + T(4) * d2);
-  fd[1] = f[1] - (-d1 - T(2) * d2 + d3 - T(2) * d4 + d7);
-  fd[2] = f[2] - (-d1 - T(2) * d2 + d5 - T(2) * d6 - d7);
-  fd[3] = f[3] - (-d1 - T(2) * d2 - d3 + T(2) * d4 + d7);
-  fd[4] = f[4] - (-d1 - T(2) * d2 - d5 + T(2) * d6 - d7);
-  fd[5] = f[5] - (T(2) * d1 + d2 + d3 + d4 + d5 + d6 + d8);
-  fd[6] = f[6] - (T(2) * d1 + d2 - d3 - d4 + d5 + d6 - d8);
-  fd[7] = f[7] - (T(2) * d1 + d2 - d3 - d4 - d5 - d6 + d8);
-  fd[8] = f[8] - (T(2) * d1 + d2 + d3 + d4 - d5 - d6 - d8);
+  // f' = f - M^T d, with the shared parts of the columns of M^T
+  const T ax = -d1 - T(2) * d2, bx = T(2) * d1 + d2;
+  const T a17 = ax + d7, a27 = ax - d7, e34 = d3 - T(2) * d4, e56 = d5 - T(2) * d6;
+  const T u8 = bx + d8, v8 = bx - d8, xy = (d3 + d4) + (d5 + d6), yx = (d5 + d6) - (d3 + d4);
+  fd[0] = f[0] - (T(4) * d2 - T(4) * d1);
+  fd[1] = f[1] - (a17 + e34);
+  fd[2] = f[2] - (a27 + e56);
+  fd[3] = f[3] - (a17 - e34);
+  fd[4] = f[4] - (a27 - e56);
+  fd[5] = f[5] - (u8 + xy);
+  fd[6] = f[6] - (v8 + yx);
+  fd[7] = f[7] - (u8 - xy);
+  fd[8] = f[8] - (v8 - yx);
 }
 
 // Eq. (13)-(15): R_k = sum_{l != k} beta_kl (rho_k rho_l / rho) n_kl for k = 1, 2

@@ -89,6 +89,17 @@ struct FillNode {
   FluidMask mask;         // fluid indicator of the block around the node
 };
 
+// A characteristic line's crossing D for one of the angles Eq. (21) gives when at most two fluids
+// are present at D0 (theta13 or theta12 for fluid 1, theta23 or theta21 for fluid 2, or the mean
+// of the pair when neither of the other two is present): the two interpolation nodes as plane
+// indices (a < 0: the line reaches no fluid) and the weight, C(D) = C(a) + w (C(b) - C(a)).
+// Formed once in FP64 at set-up (and when the angles change) with the march of the fill.
+struct FillCand {
+  int32_t a, b;
+  double w;
+};
+constexpr int kFillCands = 3;  // candidate angles per fluid
+
 // A fluid node with interpolated-bounce-back links: q[a-1] for direction a = 1..8 is the
 // fraction of the link from the node towards x - e_a at which the wall lies (1/2 when the link
 // is not cut by a circle).

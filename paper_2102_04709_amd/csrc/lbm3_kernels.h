@@ -16,6 +16,7 @@ struct FillArgs {
   const FillBlock *blocks;  // the work-groups' fill ranges
   int n_blocks;
   const uint32_t *far;      // [kFarW * n_fill] far fluid masks of the fill nodes
+  const FillCand *cand;     // [n_fill][4 lines][kFillCands] crossings of the pure-composition angles
   const DomainDev *doms;
   const uint8_t *flags;
   const T *rho;  // density planes of the current state

@@ -56,7 +56,8 @@ __global__ __launch_bounds__(4 * kFillNodes) void wet_fill(FillArgs<T> A) {
     __syncthreads();
   };
   double c1, c2;
-  fill_lanes<T>(fn, D, A.flags + D.base, A.rho + 3 * D.base, far[e], stage, line, active, c1, c2);
+  fill_lanes<T>(fn, D, A.flags + D.base, A.rho + 3 * D.base, far[e], stage, line, active, c1, c2,
+                A.cand + ((size_t)idx * 4 + line) * kFillCands);
   if (active && line == 0) {
     A.fillC[3 * idx] = (T)c1;
     A.fillC[3 * idx + 1] = (T)c2;

@@ -199,6 +199,29 @@ def capillary_intrusion(nx=1024, ny=64, ratio=1.0, slug=200, lg=200,
                     solid, _phases([m1, m2], solid))
 
 
+def intrusion_sec3c(theta_gr=60.0, theta_gb=30.0, mu=(0.35, 0.35, 0.35), L=450, H=30, s0=50, Lg=100,
+                    name=None) -> Workload:
+    """Sec. III C with the paper's labels (red -> 1, green -> 2, blue -> 3): a capillary tube of
+    length L and width H (solid rows 0 and H+1, so H fluid rows between halfway walls), red on
+    x < s0, green on s0 <= x < s0 + Lg, blue beyond; the modified periodic x boundary exchanges red
+    and blue; equal tensions 0.01; viscosities mu = (mu_r, mu_g, mu_b) (mu_k = nu_k, rho_k^0 = 1).
+    The wall angles theta_gr and theta_gb (inside green) enter as theta13 = theta_rb with
+    cos theta_br = cos theta_gr - cos theta_gb (Eq. 18, equal tensions) and theta23 = theta_gb.
+    s0 and Lg are not given in the paper (chosen here)."""
+    nx, ny = L, H + 2
+    x, y = _grid(nx, ny)
+    solid = _walls(nx, ny)
+    fl = solid == 0
+    rho = np.zeros((3, ny, nx))
+    rho[0][(x < s0) & fl] = 1.0
+    rho[1][(x >= s0) & (x < s0 + Lg) & fl] = 1.0
+    rho[2][(x >= s0 + Lg) & fl] = 1.0
+    c_br = math.cos(math.radians(theta_gr)) - math.cos(math.radians(theta_gb))
+    theta13 = 180.0 - math.degrees(math.acos(c_br))
+    return Workload(name or f"intrusion_{theta_gr:g}_{theta_gb:g}_{mu[1] / mu[0]:g}_{mu[2] / mu[0]:g}", nx, ny, 0,
+                    BC_PERIODIC_SWAP13, tuple(mu), (0.01, 0.01, 0.01), (theta13, theta_gb), solid, rho)
+
+
 # ---- Sec. III D: compound droplet among random pillars -----------------------------------
 
 def _place_pillars(rng, nx, ny, count, rmin, rmax, drop, clear, gap, edge):

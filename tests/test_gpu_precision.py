@@ -86,3 +86,47 @@ def test_precision_forms_at_20k_steps():
     assert abs(ang["f32"] - ang["oracle"]) <= 1.0
     # FP16 storage: error stated, bounded loosely
     assert err["f16"] <= 5e-2 and abs(ang["f16"] - ang["oracle"]) <= 5.0
+
+
+def _max_err(sim_a, sim_b, ws):
+    out = []
+    for d, w in enumerate(ws):
+        ra = sim_a.fields(d, velocity=False, force=False)["rho"].double().cpu().numpy()
+        rb = sim_b.fields(d, velocity=False, force=False)["rho"].double().cpu().numpy()
+        out.append(float(np.abs(ra - rb)[:, w.solid == 0].max()))
+    return out
+
+
+@pytest.mark.parametrize("ratio", [1.0, 100.0])
+def test_fp32_error_capillary_50k_steps(ratio):
+    """The 1024 x 64 ternary capillary workload (exchanging-periodic x, viscosity ratio up to 100,
+    so tau reaches 3.5 in fluid 1) after its 50 000 steps: FP32 against the FP64 GPU path, which
+    stands in for the oracle at this length (it matches the oracle to 1e-10 after 100 steps on
+    the same workload, tests/test_gpu_parity.py).  Stated error: max |d rho_k|."""
+    lbm3 = _lbm3()
+    w = W.capillary_intrusion(ratio=ratio)
+    sims = {p: lbm3.Simulation(w, precision=p, graph_block_steps=100) for p in ("f64", "f32")}
+    for p, s in sims.items():
+        s.step(50000)
+    err = _max_err(sims["f32"], sims["f64"], [w])[0]
+    print(f"capillary 1024x64 ratio {ratio}: FP32 vs FP64 max |d rho_k| after 50000 steps = {err:.3e}", flush=True)
+    for s in sims.values():
+        s.close()
+    assert err <= 1e-4
+
+
+def test_fp32_error_pillar_sweep_10k_steps():
+    """The 96-domain pillar sweep after its 10 000 steps: FP32 (one batched launch per step) against
+    the FP64 GPU path per domain (stand-in for the oracle, parity-checked on sampled domains after 20
+    steps).  Stated error: the largest max |d rho_k| over the domains, and its median."""
+    lbm3 = _lbm3()
+    ws = W.pillar_sweep()
+    sims = {p: lbm3.Simulation(ws, precision=p, graph_block_steps=10) for p in ("f64", "f32")}
+    for s in sims.values():
+        s.step(10000)
+    errs = _max_err(sims["f32"], sims["f64"], ws)
+    print(f"pillar sweep 96 domains: FP32 vs FP64 after 10000 steps: max {max(errs):.3e}, "
+          f"median {float(np.median(errs)):.3e}", flush=True)
+    for s in sims.values():
+        s.close()
+    assert max(errs) <= 1e-4
