@@ -20,7 +20,8 @@ enum {
   AX_N = 4,      // 6: pair normals (fluid nodes)
   AX_F = 10,     // 2: interfacial force (fluid nodes)
   AX_P = 12,     // 9: post-collision shifted f (fluid nodes of the two columns next to a Zou-He
-                 //    outlet, whose node reads its neighbours'; elsewhere recomputed where needed)
+                 //    outlet, whose node reads its neighbours', and nodes flagged FL_IBBSRC, whose
+                 //    neighbour's interpolated bounce-back reads them; elsewhere recomputed)
   AL_F = 21,     // 2: adjoint of F (fluid nodes)
   AL_N = 23,     // 6: adjoint of n (fluid nodes)
   AL_C = 29,     // 4: adjoint of C_k and rho

@@ -158,26 +158,13 @@ __device__ __forceinline__ T zh_add(const DomainDev &D, bool inlet, int d, const
 //   - x itself, for each of its own solid links (halfway or interpolated bounce-back).
 // No atomics: every adjoint of x's data is written by x's thread, which then applies the
 // collision transpose to them at once (adj_node).
-// Post-collision shifted population f'_dir of the fluid node (i, j) (mapped), recomputed from the
-// forward state and intermediates with the forward's own collision (bit-identical to the value
-// the forward step formed): the interpolated bounce-back of a neighbour reads it.
+// Post-collision shifted population f'_dir of the fluid node (i, j) (mapped) that the interpolated
+// bounce-back of a neighbour reads: the intermediates kernel stores the post-collision populations
+// of such nodes (flag FL_IBBSRC), formed with the forward's own collision.
 template <typename S, typename T>
-__device__ __noinline__ T nb_post_collision(const AdjArgs<S, T> &A, const DomainDev &D, const KT<T> &K, int i, int j,
-                                            int dir) {
+__device__ __forceinline__ T nb_post_collision(const AdjArgs<S, T> &A, const DomainDev &D, int i, int j, int dir) {
   cmap(D, i, j);
-  const int64_t li = plane_index(i, j, D.pitch), q = aidx(D, i, j), AP = A.aplane;
-  T f[9], fd[9], ux, uy;
-#pragma unroll
-  for (int a = 0; a < 9; ++a) f[a] = load_s<S, T>(A.fin + 9 * D.base + a * D.plane + li);
-  const T rt = A.X[(AX_C + 3) * AP + q];
-  T Fx = A.X[AX_F * AP + q], Fy = A.X[(AX_F + 1) * AP + q];
-  collide_shifted(f, Fx, Fy, A.X[AX_C * AP + q] * rt, A.X[(AX_C + 1) * AP + q] * rt, A.X[(AX_C + 2) * AP + q] * rt, K,
-                  fd, ux, uy);
-  T r = fd[0];
-#pragma unroll
-  for (int a = 1; a < 9; ++a)
-    if (a == dir) r = fd[a];
-  return r;
+  return A.X[(AX_P + dir) * A.aplane + aidx(D, i, j)];
 }
 
 template <typename S, typename T>
@@ -272,7 +259,7 @@ __device__ __forceinline__ void stream_gather(const AdjArgs<S, T> &A, const Doma
     T v;
     if (qd < T(0.5) && !((lk >> a) & 1)) {
       const T c1 = T(2) * qd, c2 = T(1) - T(2) * qd;
-      v = c1 * fp[ab] + c2 * nb_post_collision(A, D, K, i + ex, j + ey, ab);
+      v = c1 * fp[ab] + c2 * nb_post_collision(A, D, i + ex, j + ey, ab);
       lP[ab] += c1 * g;  // (the neighbour's share is gathered there)
     } else if (qd < T(0.5)) {
       v = fp[ab];

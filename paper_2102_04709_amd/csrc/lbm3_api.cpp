@@ -396,6 +396,13 @@ bool validate_and_build(const lbm3_domain &d, int dom, double beta0, DomHost &H,
         if (found) {
           node.q[a - 1] = std::min(std::max(q, 1e-6), 1.0);
           any = true;
+          // a cut link with q < 1/2 reads the post-collision population of the fluid node behind
+          if (node.q[a - 1] < 0.5 && fluid_at(i + kEX[a], j + kEY[a])) {
+            int bi = i + kEX[a], bj = j + kEY[a];
+            if (!zh) bi = ((bi % nx) + nx) % nx;
+            if (yper) bj = ((bj % ny) + ny) % ny;
+            H.flags[plane_index(bi, bj, pitch)] |= FL_IBBSRC;
+          }
         }
       }
       if (any) {

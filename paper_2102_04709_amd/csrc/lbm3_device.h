@@ -105,8 +105,8 @@ __device__ __forceinline__ double cfrac_at(const T *r, int64_t P, int64_t q, int
 // right before the march (it places the node's far mask at `far_rows`, a work-group barrier).
 // cand (may be null): the line's crossings for the pure-composition angles of its fluid; when C at
 // D0 leaves Eq. (21) one of them (the other two fluids' weights below 1e-15 of their sum, or both
-// absent) the line takes that crossing instead of marching, and the densities at its nodes are
-// loaded together with those of D0.
+// absent) the line takes that crossing instead of marching.  The densities at the first candidate's
+// nodes (the angle against fluid 3, the usual ambient) are loaded together with those of D0.
 template <typename T, class Stage>
 __device__ __forceinline__ void fill_lanes(const FillNode &fn, const DomainDev &D, const uint8_t *flags,
                                            const T *r, const uint32_t *far_rows, const Stage &stage, int line,
@@ -131,17 +131,15 @@ __device__ __forceinline__ void fill_lanes(const FillNode &fn, const DomainDev &
   };
   const double PI = 3.14159265358979323846;
   const int k = line >> 1;
-  // the candidate crossings' densities, loaded beside those of D0
-  FillCand cd[kFillCands];
-  T rc[kFillCands][2][3];
-#pragma unroll
-  for (int c = 0; c < kFillCands; ++c) {
-    cd[c] = cand ? cand[c] : FillCand{-1, -1, 0.0};
-    const int64_t qa = cd[c].a >= 0 ? cd[c].a : fn.d0a, qb = cd[c].a >= 0 ? cd[c].b : fn.d0a;
+  // the first candidate crossing's densities, loaded beside those of D0
+  const FillCand c0 = cand ? cand[0] : FillCand{-1, -1, 0.0};
+  T rc0[2][3];
+  {
+    const int64_t qa = c0.a >= 0 ? c0.a : fn.d0a, qb = c0.a >= 0 ? c0.b : fn.d0a;
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
-      rc[c][0][q] = r[q * P + qa];
-      rc[c][1][q] = r[q * P + qb];
+      rc0[0][q] = r[q * P + qa];
+      rc0[1][q] = r[q * P + qb];
     }
   }
   // C at D0 for the weighted contact angle of Eq. (21).
@@ -168,27 +166,17 @@ __device__ __forceinline__ void fill_lanes(const FillNode &fn, const DomainDev &
   double v = 0.0;
   int ok = 0;
   stage();
-  if (active && pick >= 0) {
-    // the precomputed crossing of this composition's angle
-    FillCand h = cd[0];
-    double ra[3], rb[3];
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      ra[q] = (double)rc[0][0][q];
-      rb[q] = (double)rc[0][1][q];
+  if (active && pick == 0) {  // the precomputed crossing whose densities are in
+    if (c0.a >= 0) {
+      const double ca = (double)rc0[0][k] / ((double)rc0[0][0] + (double)rc0[0][1] + (double)rc0[0][2]);
+      const double cb = (double)rc0[1][k] / ((double)rc0[1][0] + (double)rc0[1][1] + (double)rc0[1][2]);
+      v = ca + c0.w * (cb - ca);
+      ok = 1;
     }
-#pragma unroll
-    for (int c = 1; c < kFillCands; ++c)
-      if (pick == c) {
-        h = cd[c];
-#pragma unroll
-        for (int q = 0; q < 3; ++q) {
-          ra[q] = (double)rc[c][0][q];
-          rb[q] = (double)rc[c][1][q];
-        }
-      }
+  } else if (active && pick > 0) {  // another precomputed crossing
+    const FillCand h = cand[pick];
     if (h.a >= 0) {
-      const double ca = ra[k] / (ra[0] + ra[1] + ra[2]), cb = rb[k] / (rb[0] + rb[1] + rb[2]);
+      const double ca = cfrac_at(r, P, h.a, k), cb = cfrac_at(r, P, h.b, k);
       v = ca + h.w * (cb - ca);
       ok = 1;
     }
@@ -295,28 +283,27 @@ __device__ __forceinline__ bool pair_norm(double gx, double gy, double eps, doub
 // Eq. (10) stress sum over the fluid pairs 12, 13, 23 (the double sum over ordered pairs with
 // the factor 1/2 equals the sum over unordered pairs, since G_lk = -G_kl), and the pair normals
 // n_kl = G_kl / |G_kl| (zero when |G_kl| <= eps).
-// The pair term sigma A |G| (I - n n^T) is written as (sigma A / |G|) (Gy^2, -Gx Gy, Gx^2).
 template <typename T>
 __device__ __forceinline__ void pair_stress(const T cc[3], const T g[3][2], T rho, const KT<T> &K,
                                             T eps, T &txx, T &txy, T &tyy, T nrm[6]) {
   txx = txy = tyy = T(0);
   const int pk[3] = {0, 0, 1}, pl[3] = {1, 2, 2};
-  const T r[3] = {cc[0] * rho, cc[1] * rho, cc[2] * rho};
 #pragma unroll
   for (int pr = 0; pr < 3; ++pr) {
     const int k = pk[pr], l = pl[pr];
     const T Gx = cc[l] * g[k][0] - cc[k] * g[l][0];
     const T Gy = cc[l] * g[k][1] - cc[k] * g[l][1];
-    const T Akl = fmin(fmax(T(1e6) * r[k] * r[l], T(0)), T(1));
+    const T rk = cc[k] * rho, rl = cc[l] * rho;
+    const T Akl = fmin(fmax(T(1e6) * rk * rl, T(0)), T(1));
     T mag, im;
     if (pair_norm(Gx, Gy, eps, mag, im)) {
-      const T c = K.sig[pr] * Akl * im;
-      const T cx = c * Gx, cy = c * Gy;
-      txx += cy * Gy;
-      txy -= cx * Gy;
-      tyy += cx * Gx;
-      nrm[2 * pr] = Gx * im;
-      nrm[2 * pr + 1] = Gy * im;
+      const T nx = Gx * im, ny = Gy * im;
+      const T coef = K.sig[pr] * Akl * mag;
+      txx += coef * (T(1) - nx * nx);
+      txy += coef * (-nx * ny);
+      tyy += coef * (T(1) - ny * ny);
+      nrm[2 * pr] = nx;
+      nrm[2 * pr + 1] = ny;
     } else {
       nrm[2 * pr] = T(0);
       nrm[2 * pr + 1] = T(0);
@@ -339,20 +326,16 @@ __device__ __forceinline__ void div_stress(const T *xx, const T *xy, const T *yy
 template <typename T>
 __device__ __forceinline__ void collide_shifted(const T f[9], T &Fx, T &Fy, T r0, T r1, T r2,
                                                 const KT<T> &K, T fd[9], T &ux, T &uy) {
-  // moments m = M f (Eq. 4) with shared partial sums
-  const T s13 = f[1] + f[3], s24 = f[2] + f[4], s57 = f[5] + f[7], s68 = f[6] + f[8];
-  const T s14 = s13 + s24, s58 = s57 + s68;
-  const T d13 = f[1] - f[3], d24 = f[2] - f[4], d58 = f[5] - f[8], d67 = f[6] - f[7];
-  const T qx = (f[5] - f[6]) - (f[7] - f[8]), qy = d58 + d67;  // f5 - f6 - f7 + f8, f5 + f6 - f7 - f8
+  const T s14 = f[1] + f[2] + f[3] + f[4], s58 = f[5] + f[6] + f[7] + f[8];
   const T drho = f[0] + s14 + s58;
   const T m1 = -T(4) * f[0] - s14 + T(2) * s58;
   const T m2 = T(4) * f[0] - T(2) * s14 + s58;
-  const T jx = d13 + qx;
-  const T m4 = qx - T(2) * d13;
-  const T jy = d24 + qy;
-  const T m6 = qy - T(2) * d24;
-  const T m7 = s13 - s24;
-  const T m8 = s57 - s68;
+  const T jx = f[1] - f[3] + f[5] - f[6] - f[7] + f[8];
+  const T m4 = -T(2) * f[1] + T(2) * f[3] + f[5] - f[6] - f[7] + f[8];
+  const T jy = f[2] - f[4] + f[5] + f[6] - f[7] - f[8];
+  const T m6 = -T(2) * f[2] + T(2) * f[4] + f[5] + f[6] - f[7] - f[8];
+  const T m7 = f[1] - f[2] + f[3] - f[4];
+  const T m8 = f[5] - f[6] + f[7] - f[8];
   const T rho = T(1) + drho;
   Fx += rho * K.g0;
   Fy += rho * K.g1;
@@ -375,19 +358,16 @@ __device__ __forceinline__ void collide_shifted(const T f[9], T &Fx, T &Fy, T r0
   const T d6 = (s4 * (m6 + rho * uy) + h4 * Fy) * T(1.0 / 12.0);
   const T d7 = (s1 * (m7 - rho * (ux * ux - uy * uy)) - h1 * T(2) * (ux * Fx - uy * Fy)) * T(0.25);
   const T d8 = (s1 * (m8 - rho * ux * uy) - h1 * (ux * Fy + uy * Fx)) * T(0.25);
-  // f' = f - M^T d, with the shared parts of the columns of M^T
-  const T ax = -d1 - T(2) * d2, bx = T(2) * d1 + d2;
-  const T a17 = ax + d7, a27 = ax - d7, e34 = d3 - T(2) * d4, e56 = d5 - T(2) * d6;
-  const T u8 = bx + d8, v8 = bx - d8, xy = (d3 + d4) + (d5 + d6), yx = (d5 + d6) - (d3 + d4);
-  fd[0] = f[0] - (T(4) * d2 - T(4) * d1);
-  fd[1] = f[1] - (a17 + e34);
-  fd[2] = f[2] - (a27 + e56);
-  fd[3] = f[3] - (a17 - e34);
-  fd[4] = f[4] - (a27 - e56);
-  fd[5] = f[5] - (u8 + xy);
-  fd[6] = f[6] - (v8 + yx);
-  fd[7] = f[7] - (u8 - xy);
-  fd[8] = f[8] - (v8 - yx);
+  // f' = f - M^T d
+  fd[0] = f[0] - (-T(4) * d1 + T(4) * d2);
+  fd[1] = f[1] - (-d1 - T(2) * d2 + d3 - T(2) * d4 + d7);
+  fd[2] = f[2] - (-d1 - T(2) * d2 + d5 - T(2) * d6 - d7);
+  fd[3] = f[3] - (-d1 - T(2) * d2 - d3 + T(2) * d4 + d7);
+  fd[4] = f[4] - (-d1 - T(2) * d2 - d5 + T(2) * d6 - d7);
+  fd[5] = f[5] - (T(2) * d1 + d2 + d3 + d4 + d5 + d6 + d8);
+  fd[6] = f[6] - (T(2) * d1 + d2 - d3 - d4 + d5 + d6 - d8);
+  fd[7] = f[7] - (T(2) * d1 + d2 - d3 - d4 - d5 - d6 + d8);
+  fd[8] = f[8] - (T(2) * d1 + d2 + d3 + d4 - d5 - d6 - d8);
 }
 
 // Eq. (13)-(15): R_k = sum_{l != k} beta_kl (rho_k rho_l / rho) n_kl for k = 1, 2

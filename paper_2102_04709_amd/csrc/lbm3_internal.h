@@ -35,6 +35,8 @@ enum : uint8_t {
   FL_SOLID = 1,   // solid node (mask, or off-grid row of a non-periodic y boundary)
   FL_FILL = 2,    // solid node whose C is filled by the wetting condition (C_SB or C_SB2)
   FL_CURVED = 4,  // fluid node with at least one interpolated-bounce-back link
+  FL_IBBSRC = 8,  // fluid node whose post-collision population a neighbour's interpolated
+                  // bounce-back reads (a link cut at q < 1/2 with this node behind it)
 };
 
 enum { BCX_PERIODIC = 0, BCX_SWAP13 = 1, BCX_ZOUHE = 2 };

@@ -255,7 +255,9 @@ __global__ __launch_bounds__(NT, sizeof(T) == 8 ? 1 : (sizeof(S) == 2 ? 5 : 6)) 
         const int64_t a = adj_index(D, gx, gy);
         A.adj_X[AX_F * A.adj_plane + a] = Fx;
         A.adj_X[(AX_F + 1) * A.adj_plane + a] = Fy;
-        if (!zh_out) continue;  // the collision below only where a Zou-He outlet node reads it
+        // the collision below only where a Zou-He outlet node or a neighbour's interpolated
+        // bounce-back reads its result
+        if (!zh_out && !(L.FL[p3] & FL_IBBSRC)) continue;
       }
       T f[9];
       {
@@ -274,8 +276,8 @@ __global__ __launch_bounds__(NT, sizeof(T) == 8 ? 1 : (sizeof(S) == 2 ? 5 : 6)) 
         if (A.out_force) { A.out_force[o] = Fx; A.out_force[n + o] = Fy; }
         continue;
       }
-      if (ADJ) {  // the post-collision populations in the two columns a Zou-He outlet node
-                  // reads them from (the adjoint's node kernel recomputes its own elsewhere)
+      if (ADJ) {  // the post-collision populations that a Zou-He outlet node or an interpolated
+                  // bounce-back reads (the adjoint's node kernel recomputes its own elsewhere)
         const int64_t a = adj_index(D, gx, gy);
 #pragma unroll
         for (int c = 0; c < 9; ++c) A.adj_X[(AX_P + c) * A.adj_plane + a] = fd[c];

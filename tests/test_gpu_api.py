@@ -45,3 +45,29 @@ def test_tune_cache_round_trip(tmp_path):
     s3.autotune(2)
     s3.close()
     assert len(json.load(open(path))) == 2
+
+
+def test_non_finite_density_is_reported():
+    """Failure detection: a NaN planted in the state (at one fluid node's first partial density)
+    makes lbm3_mass return LBM3_ENUMERIC, and the allocation-free mass shows a non-finite sum;
+    stepping on goes on without a fault."""
+    torch, lbm3 = _mods()
+    w = W.random_mixture(48, 24, seed=8, walls=True)
+    sim = lbm3.Simulation(w, precision="f32")
+    sim.step(3)
+    st = sim.get_state()
+    f = st.view(torch.float32)
+    pitch = (w.nx + 63) // 64 * 64
+    plane = pitch * (w.ny + 4)
+    j, i = 10, 20
+    assert w.solid[j, i] == 0
+    f[9 * plane + i + pitch * (j + 2)] = float("nan")
+    sim.set_state(st)
+    with pytest.raises(lbm3.Lbm3Error) as e:
+        sim.mass()
+    assert e.value.code == lbm3.LBM3_ENUMERIC
+    sim.step(2)
+    m = sim.mass_device()
+    torch.cuda.synchronize()
+    assert not bool(torch.isfinite(m).all())
+    sim.close()
