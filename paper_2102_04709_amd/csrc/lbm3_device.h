@@ -19,6 +19,14 @@ __host__ __device__ constexpr int lat_opp(int a) { return a == 0 ? 0 : (a <= 4 ?
 static_assert(lat_opp(1) == 3 && lat_opp(2) == 4 && lat_opp(3) == 1 && lat_opp(4) == 2, "opposites");
 static_assert(lat_opp(5) == 7 && lat_opp(6) == 8 && lat_opp(7) == 5 && lat_opp(8) == 6, "opposites");
 
+// e.(x, y) for lattice components in {-1, 0, 1} (compile-time after unrolling), written without
+// products by zero: x * 0 does not fold away under IEEE rules, and the sum is exact either way.
+template <typename T>
+__device__ __forceinline__ T edot(int ex, int ey, T x, T y) {
+  const T tx = ex > 0 ? x : -x, ty = ey > 0 ? y : -y;
+  return ex == 0 ? (ey == 0 ? T(0) : ty) : (ey == 0 ? tx : tx + ty);
+}
+
 template <typename T>
 __device__ __forceinline__ T wgt(int a) {
   return a == 0 ? T(4.0 / 9.0) : (a < 5 ? T(1.0 / 9.0) : T(1.0 / 36.0));
@@ -401,15 +409,26 @@ __device__ __forceinline__ const IbbNode *find_ibb(const IbbNode *ibb, const Dom
 // Recoloured populations f''_{dir,k} of Eq. (13) at a node (through the accessor): C_k (f'+w)
 // + w R_k.e_dir.
 template <typename T, class Acc>
-__device__ __forceinline__ void fluid_parts(const Acc &acc, int dx, int dy, int dir, T out[3]) {
+__device__ __forceinline__ void fluid_parts_of(const Acc &acc, int dx, int dy, int dir, T fv, T out[3]) {
   const T w = wgt<T>(dir);
   const int ex = lat_ex(dir), ey = lat_ey(dir);
-  const T fv = acc.f(dir, dx, dy) + w;
-  const T R1 = acc.R(0, dx, dy) * ex + acc.R(1, dx, dy) * ey;
-  const T R2 = acc.R(2, dx, dy) * ex + acc.R(3, dx, dy) * ey;
+  if (dir == 0) {  // e = 0: no recolouring term
+    out[0] = acc.C(0, dx, dy) * fv;
+    out[1] = acc.C(1, dx, dy) * fv;
+    out[2] = acc.C(2, dx, dy) * fv;
+    return;
+  }
+  const T R1 = edot<T>(ex, ey, acc.R(0, dx, dy), acc.R(1, dx, dy));
+  const T R2 = edot<T>(ex, ey, acc.R(2, dx, dy), acc.R(3, dx, dy));
   out[0] = acc.C(0, dx, dy) * fv + w * R1;
   out[1] = acc.C(1, dx, dy) * fv + w * R2;
   out[2] = acc.C(2, dx, dy) * fv + w * (-(R1 + R2));
+}
+
+// The same for the node's own post-collision population (shifted) in direction dir.
+template <typename T, class Acc>
+__device__ __forceinline__ void fluid_parts(const Acc &acc, int dx, int dy, int dir, T out[3]) {
+  fluid_parts_of<T>(acc, dx, dy, dir, acc.f(dir, dx, dy) + wgt<T>(dir), out);
 }
 
 // Eq. (16) pull-streaming into a fluid node whose eight neighbours are fluid and whose links cross
@@ -458,8 +477,6 @@ __device__ __forceinline__ void stream_node(const Acc &acc, int gx, const Domain
       const int ab = lat_opp(a);
       const T qd = ib ? (T)ib->q[a - 1] : T(0.5);
       const T fab = acc.f(ab, 0, 0);
-      T own_ab[3];
-      fluid_parts<T>(acc, 0, 0, ab, own_ab);
       T v;
       if (qd < T(0.5) && !acc.solid(ex, ey)) {
         const T c1 = T(2) * qd, c2 = T(1) - T(2) * qd;
@@ -471,10 +488,12 @@ __device__ __forceinline__ void stream_node(const Acc &acc, int gx, const Domain
         v = c1 * fab + c2 * acc.f(a, 0, 0);
       }
       fo[a] = v;
-      const T dv = v - fab;  // zero at q = 1/2: halfway bounce-back exactly
-      ra += own_ab[0] + acc.C(0, 0, 0) * dv;
-      rb += own_ab[1] + acc.C(1, 0, 0) * dv;
-      rc += own_ab[2] + acc.C(2, 0, 0) * dv;
+      // Eq. (13) at x with the reflected total v in place of f'_ab (at q = 1/2, v = f'_ab)
+      T own_ab[3];
+      fluid_parts_of<T>(acc, 0, 0, ab, v + wgt<T>(ab), own_ab);
+      ra += own_ab[0];
+      rb += own_ab[1];
+      rc += own_ab[2];
     }
   }
   if (D.bcx == BCX_ZOUHE && (gx == 0 || gx == D.nx - 1)) {

@@ -104,6 +104,13 @@ struct TileAcc {
   int p1, p3;
   __device__ bool solid(int dx, int dy) const { return L.FL[p3 + dx + dy * W3] & FL_SOLID; }
   __device__ T f(int dir, int dx, int dy) const { return L.PF[dir * N1 + p1 + dx + dy * W1]; }
+  // f for a rarely taken branch: the index is formed where it is used (an opaque copy of p1 keeps
+  // the compiler from computing such indices for every link up front and holding them live)
+  __device__ T f_rare(int dir, int dx, int dy) const {
+    int p = p1;
+    asm volatile("" : "+v"(p));
+    return L.PF[dir * N1 + p + dx + dy * W1];
+  }
   __device__ T R(int c, int dx, int dy) const { return L.PR[c * N1 + p1 + dx + dy * W1]; }
   __device__ T C(int k, int dx, int dy) const {
     const int q = p3 + dx + dy * W3;
@@ -384,6 +391,7 @@ struct StripAcc {
   int cs[3], ps[3];       // C / post-collision ring slots of rows y-1, y, y+1
   __device__ bool solid(int dx, int dy) const { return Fr[cs[dy + 1] * NT + c + dx] & FL_SOLID; }
   __device__ T f(int dir, int dx, int dy) const { return Pr[(ps[dy + 1] * 13 + dir) * NT + c + dx]; }
+  __device__ T f_rare(int dir, int dx, int dy) const { return f(dir, dx, dy); }
   __device__ T R(int k, int dx, int dy) const { return Pr[(ps[dy + 1] * 13 + 9 + k) * NT + c + dx]; }
   __device__ T C(int k, int dx, int dy) const { return Cr[(cs[dy + 1] * 4 + k) * NT + c + dx]; }
 };
