@@ -153,9 +153,11 @@ struct LineHit {
   double w;            // value = v(i0, j0) + w * (v(i1, j1) - v(i0, j0))
 };
 
+// kx, ky: the indices of the next vertical and horizontal crossings to visit (1, 1 from the
+// node; a march that resumes another one's passes that march's state).
 template <class FluidAt>
 __host__ __device__ inline LineHit march_line(int pi, int pj, double dx, double dy,
-                                              const FluidAt &fluid) {
+                                              const FluidAt &fluid, int kx = 1, int ky = 1) {
   LineHit h;
   h.ok = 0;
   h.i0 = h.j0 = h.i1 = h.j1 = 0;
@@ -164,7 +166,6 @@ __host__ __device__ inline LineHit march_line(int pi, int pj, double dx, double 
   const int sy = dy > kEpsDir ? 1 : (dy < -kEpsDir ? -1 : 0);
   const double ax = dx < 0 ? -dx : dx, ay = dy < 0 ? -dy : dy;
   const double iax = sx ? 1.0 / ax : 0.0, iay = sy ? 1.0 / ay : 0.0;
-  int kx = 1, ky = 1;
   for (int guard = 0; guard < 256; ++guard) {
     const double tx = sx ? (double)kx * iax : 1e300;  // t of the next vertical line
     const double ty = sy ? (double)ky * iay : 1e300;  // t of the next horizontal line
@@ -216,10 +217,12 @@ __host__ __device__ inline LineHit march_line(int pi, int pj, double dx, double 
 // march_line with the fluid tests of a (2R + 1)^2 block around the node answered by test(dx, dy)
 // (a bit mask, no memory access): the same crossings in the same order with the same arithmetic,
 // so its hit is march_line's.  A line that needs a node outside the block (or more crossings than
-// the block can hold) before it hits is handed to fallback() from the start.
+// the block can hold) before it hits is handed to fallback(kx, ky) at that crossing: every
+// crossing before it failed the block's test, which agrees with the fallback's on the block, so
+// the fallback's first hit from there is the line's.  kx, ky: as for march_line.
 template <int R, class BlockTest, class Fallback>
 __host__ __device__ inline LineHit march_line_block(int pi, int pj, double dx, double dy, const BlockTest &test,
-                                                    const Fallback &fallback) {
+                                                    const Fallback &fallback, int kx = 1, int ky = 1) {
   LineHit h;
   h.ok = 0;
   h.i0 = h.j0 = h.i1 = h.j1 = 0;
@@ -228,7 +231,6 @@ __host__ __device__ inline LineHit march_line_block(int pi, int pj, double dx, d
   const int sy = dy > kEpsDir ? 1 : (dy < -kEpsDir ? -1 : 0);
   const double ax = dx < 0 ? -dx : dx, ay = dy < 0 ? -dy : dy;
   const double iax = sx ? 1.0 / ax : 0.0, iay = sy ? 1.0 / ay : 0.0;
-  int kx = 1, ky = 1;
   for (int it = 0; it < 4 * R + 2; ++it) {
     const double tx = sx ? (double)kx * iax : 1e300;  // t of the next vertical line
     const double ty = sy ? (double)ky * iay : 1e300;  // t of the next horizontal line
@@ -239,6 +241,11 @@ __host__ __device__ inline LineHit march_line_block(int pi, int pj, double dx, d
     const double cr = floor(c + 0.5);
     const bool node = fabs(c - cr) < kEpsNode;
     const int c0 = node ? (int)cr : (int)floor(c);
+    // block offsets of the crossing's node (node) or of its two interpolation nodes; a crossing
+    // outside the block goes to the fallback before the indices move past it
+    const int a0 = vert ? line - pi : c0 - pi, b0 = vert ? c0 - pj : line - pj;
+    const int a1 = (vert || node) ? a0 : a0 + 1, b1 = (vert && !node) ? b0 + 1 : b0;
+    if (a0 < -R || a1 > R || b0 < -R || b1 > R) break;
     if (vert) {
       ++kx;
       if (node && sy && c0 == pj + sy * ky) ++ky;
@@ -246,10 +253,6 @@ __host__ __device__ inline LineHit march_line_block(int pi, int pj, double dx, d
       ++ky;
       if (node && sx && c0 == pi + sx * kx) ++kx;
     }
-    // block offsets of the crossing's node (node) or of its two interpolation nodes
-    const int a0 = vert ? line - pi : c0 - pi, b0 = vert ? c0 - pj : line - pj;
-    const int a1 = (vert || node) ? a0 : a0 + 1, b1 = (vert && !node) ? b0 + 1 : b0;
-    if (a0 < -R || a1 > R || b0 < -R || b1 > R) break;
     if (test(a0, b0) && test(a1, b1)) {
       h.ok = 1;
       h.i0 = pi + a0; h.j0 = pj + b0; h.i1 = pi + a1; h.j1 = pj + b1;
@@ -257,12 +260,13 @@ __host__ __device__ inline LineHit march_line_block(int pi, int pj, double dx, d
       return h;
     }
   }
-  return fallback();
+  return fallback(kx, ky);
 }
 
-// The wetting fill's march: the 11 x 11 mask of the fill record first; a line leaving it is
-// marched again over the 25 x 25 block of the node's far mask (rows of 25 bits, offsets -12..12,
-// bit dx + 12 of row dy + 12); beyond that march_line reads the flags.
+// The wetting fill's march: the 11 x 11 mask of the fill record first; a line leaving it
+// continues, from the crossing where it left, over the 25 x 25 block of the node's far mask (rows
+// of 25 bits, offsets -12..12, bit dx + 12 of row dy + 12); beyond that march_line continues over
+// the flags.
 constexpr int kFarR = 12, kFarW = 2 * kFarR + 1;
 
 template <class FluidAt>
@@ -270,8 +274,8 @@ __host__ __device__ inline LineHit march_line_masked(int pi, int pj, double dx, 
                                                      const uint32_t *far_rows, const FluidAt &fluid) {
   auto near_test = [&](int a, int b) { return mask.fluid(a, b); };
   auto far_test = [&](int a, int b) { return ((far_rows[b + kFarR] >> (a + kFarR)) & 1u) != 0; };
-  auto general = [&]() { return march_line(pi, pj, dx, dy, fluid); };
-  auto far = [&]() { return march_line_block<kFarR>(pi, pj, dx, dy, far_test, general); };
+  auto general = [&](int kx, int ky) { return march_line(pi, pj, dx, dy, fluid, kx, ky); };
+  auto far = [&](int kx, int ky) { return march_line_block<kFarR>(pi, pj, dx, dy, far_test, general, kx, ky); };
   return march_line_block<kMaskR>(pi, pj, dx, dy, near_test, far);
 }
 
