@@ -66,7 +66,8 @@ typedef enum {
 /* One domain.  Equal densities rho_k^0 = 1 (Sec. II A), so the dynamic viscosity of each pure
  * fluid equals its kinematic viscosity nu_k. */
 typedef struct {
-  int32_t nx, ny;        /* lattice nodes, >= 3 each */
+  int32_t nx, ny;        /* lattice nodes, >= 3 each; (nx rounded up to 64) x (ny + 4) below
+                            2^30 (LBM3_F32, LBM3_F32_STORE_F16) or 2^29 (LBM3_F64) */
   int32_t y_periodic;    /* 1: periodic in y; 0: every node outside 0 <= y < ny is solid
                             (flat walls are solid rows inside the mask) */
   int32_t bc_x;          /* lbm3_bc_x */

@@ -433,6 +433,16 @@ bool plan(const lbm3_domain *d, int n, const lbm3_options *o, std::vector<DomHos
   }
   if (!tiles && o->tile_y > 0 && o->tile_y < kMinStripRows) return err = "strip segments need at least 8 rows", false;
   const double beta0 = o->beta0 > 0 ? o->beta0 : 0.7;
+  // The step kernels address a plane as a base plus a 32-bit byte offset: a domain's padded plane
+  // (nx rounded up to 64, rows -2..ny+1) of the arithmetic type stays below 4 GiB.
+  const int64_t max_plane = (int64_t(1) << 32) / (o->precision == LBM3_F64 ? 8 : 4);
+  for (int i = 0; i < n; ++i)
+    if (d[i].nx >= 3 && d[i].ny >= 3 && ((int64_t)d[i].nx + 63) / 64 * 64 * ((int64_t)d[i].ny + 4) >= max_plane) {
+      char m[160];
+      snprintf(m, sizeof m, "domain %d: the padded plane (nx rounded up to 64, times ny + 4) must hold fewer than %lld nodes",
+               i, (long long)max_plane);
+      return err = m, false;
+    }
   H.assign(n, DomHost());
   for (int i = 0; i < n; ++i)
     if (!validate_and_build(d[i], i, beta0, H[i], err)) return false;

@@ -8,6 +8,8 @@
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "lbm3_internal.h"
 
 namespace lbm3 {
@@ -53,6 +55,22 @@ __device__ __forceinline__ T load_s(const S *p) {
 }
 template <>
 __device__ __forceinline__ double load_s<double, double>(const double *p) { return *p; }
+
+// Element i of a plane whose base is the same for the whole wave, addressed as that base plus a
+// 32-bit byte offset: gfx950's global loads and stores take this form directly (scalar base,
+// 32-bit vector offset), so no 64-bit address is formed per lane.  The empty asm keeps the base
+// in scalar registers and stops the compiler from folding the planes' distance into the per-lane
+// address instead.  lbm3_create keeps every domain's plane of the arithmetic type below 4 GiB,
+// and plane indices are never negative.
+template <typename V>
+__device__ __forceinline__ V *elem32(V *base, int64_t i) {
+  using B = typename std::conditional<std::is_const<V>::value, const char, char>::type;
+  using GB = __attribute__((address_space(1))) B;  // the global address space (not a flat access)
+  uint64_t u = reinterpret_cast<uint64_t>(base);
+  asm("" : "+s"(u));
+  GB *g = reinterpret_cast<GB *>(u) + (uint32_t)i * (uint32_t)sizeof(V);
+  return (V *)g;
+}
 
 template <typename S, typename T>
 __device__ __forceinline__ void store_s(S *p, T v) {

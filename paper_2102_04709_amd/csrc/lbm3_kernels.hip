@@ -158,9 +158,9 @@ void step_fused(StepArgs<S, T> A) {
       const int lx = q % W3, ly = q / W3;
       const int64_t li = inner ? plane_index(x0 - 3 + lx, y0 - 3 + ly, D.pitch)
                                : node_index(x0 - 3 + lx, y0 - 3 + ly, D);
-      const uint8_t fl = flags[li];
+      const uint8_t fl = *elem32(flags, li);
       T v[4];
-      node_composition<T>(fl, Rin[li], Rin[P + li], Rin[2 * P + li], A.fillC, v);
+      node_composition<T>(fl, *elem32(Rin, li), *elem32(Rin + P, li), *elem32(Rin + 2 * P, li), A.fillC, v);
       L.FL[q] = fl;
       L.C0[q] = v[0]; L.C1[q] = v[1]; L.C2[q] = v[2];
       if (lx >= 1 && lx <= W3 - 2 && ly >= 1 && ly <= H3 - 2) L.RH[(lx - 1) + (ly - 1) * W2] = v[3];
@@ -272,7 +272,7 @@ void step_fused(StepArgs<S, T> A) {
       {
         const int64_t li = inner ? plane_index(gx, gy, D.pitch) : node_index(gx, gy, D);
 #pragma unroll
-        for (int a = 0; a < 9; ++a) f[a] = load_s<S, T>(Fin + a * P + li);
+        for (int a = 0; a < 9; ++a) f[a] = load_s<S, T>(elem32(Fin + a * P, li));
       }
       const T rt = L.RH[p2];
       const T r0 = L.C0[p3] * rt, r1 = L.C1[p3] * rt, r2 = L.C2[p3] * rt;
@@ -355,19 +355,19 @@ void step_fused(StepArgs<S, T> A) {
       // share lines with the neighbouring tile, which the L2 then merges before writing back.
       if constexpr (TX * sizeof(S) >= 128) {
 #pragma unroll
-        for (int a = 0; a < 9; ++a) store_nt<S, T>(Fout + a * P + li, fo[a]);
+        for (int a = 0; a < 9; ++a) store_nt<S, T>(elem32(Fout + a * P, li), fo[a]);
       } else {
 #pragma unroll
-        for (int a = 0; a < 9; ++a) store_s<S, T>(Fout + a * P + li, fo[a]);
+        for (int a = 0; a < 9; ++a) store_s<S, T>(elem32(Fout + a * P, li), fo[a]);
       }
       if constexpr (TX * sizeof(T) >= 128) {
-        store_nt<T, T>(Rout + li, ra);
-        store_nt<T, T>(Rout + P + li, rb);
-        store_nt<T, T>(Rout + 2 * P + li, rc);
+        store_nt<T, T>(elem32(Rout, li), ra);
+        store_nt<T, T>(elem32(Rout + P, li), rb);
+        store_nt<T, T>(elem32(Rout + 2 * P, li), rc);
       } else {
-        Rout[li] = ra;
-        Rout[P + li] = rb;
-        Rout[2 * P + li] = rc;
+        *elem32(Rout, li) = ra;
+        *elem32(Rout + P, li) = rb;
+        *elem32(Rout + 2 * P, li) = rc;
       }
     }
     __syncthreads();

@@ -70,6 +70,18 @@ def test_invalid_geometry_rejected(lib):
         _bytes([w], tile=(8, 8))  # tile area below the minimum is an invalid option at create only
 
 
+@pytest.mark.parametrize("precision,n", [("f64", 23200), ("f32", 32768), ("f16", 32768)])
+def test_oversized_plane_rejected(lib, precision, n):
+    """A domain plane whose byte offsets would not fit 32 bits is refused before any of its host
+    arrays is read (the struct is given a small workload's arrays and an oversized shape)."""
+    args = lbm3.DomainArgs([W.flat_janus()])
+    args.array[0].nx = n
+    args.array[0].ny = n
+    with pytest.raises(lbm3.Lbm3Error, match="padded plane") as e:
+        lbm3.lbm3_workspace_bytes(args, lbm3.make_options(precision=precision))
+    assert e.value.code == lbm3.LBM3_EINVAL
+
+
 def test_bad_options_rejected(lib):
     w = W.flat_janus()
     with pytest.raises(lbm3.Lbm3Error):
