@@ -275,7 +275,7 @@ def main():
             print(json.dumps({"workload": name, **r}), flush=True)
             return
         if name.startswith("adjoint_4000"):
-            r = measure_adjoint(W.cylinder_janus_hbm(10), name.rsplit("_", 1)[1], steps=6, rollout_steps=0)
+            r = measure_adjoint(W.cylinder_janus_hbm(10), name.rsplit("_", 1)[1], steps=24, rollout_steps=0)
             print(json.dumps({"workload": name, **r}), flush=True)
             return
         if name.startswith("pillar_sweep"):
@@ -329,7 +329,7 @@ def main():
             log(f"variant: adjoint step, inverse problem 512x256 {p}")
             extra[f"adjoint_512_{p}"] = measure_adjoint(W.inverse_problem(), p)
         log("adjoint step at HBM scale: 4000x4000 cylinder, f32")
-        extra["adjoint_4000_f32"] = measure_adjoint(W.cylinder_janus_hbm(10), "f32", steps=6, rollout_steps=0)
+        extra["adjoint_4000_f32"] = measure_adjoint(W.cylinder_janus_hbm(10), "f32", steps=24, rollout_steps=0)
         out["variants"] = extra
         out["roofline_hbm"] = extra["cylinder_4000_f32"]["roofline"]
     if not args.skip_cpu:
