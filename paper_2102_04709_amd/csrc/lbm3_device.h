@@ -308,11 +308,13 @@ __device__ __forceinline__ bool pair_norm(double gx, double gy, double eps, doub
 
 // Eq. (10) stress sum over the fluid pairs 12, 13, 23 (the double sum over ordered pairs with
 // the factor 1/2 equals the sum over unordered pairs, since G_lk = -G_kl), and the pair normals
-// n_kl = G_kl / |G_kl| (zero when |G_kl| <= eps).
+// n_kl = G_kl / |G_kl| (zero when |G_kl| <= eps).  Returns whether any pair had |G_kl| > eps
+// (otherwise the stress is +0 in all three components and the normals are zero).
 template <typename T>
-__device__ __forceinline__ void pair_stress(const T cc[3], const T g[3][2], T rho, const KT<T> &K,
+__device__ __forceinline__ bool pair_stress(const T cc[3], const T g[3][2], T rho, const KT<T> &K,
                                             T eps, T &txx, T &txy, T &tyy, T nrm[6]) {
   txx = txy = tyy = T(0);
+  bool any = false;
   const int pk[3] = {0, 0, 1}, pl[3] = {1, 2, 2};
 #pragma unroll
   for (int pr = 0; pr < 3; ++pr) {
@@ -323,6 +325,7 @@ __device__ __forceinline__ void pair_stress(const T cc[3], const T g[3][2], T rh
     const T Akl = fmin(fmax(T(1e6) * rk * rl, T(0)), T(1));
     T mag, im;
     if (pair_norm(Gx, Gy, eps, mag, im)) {
+      any = true;
       const T nx = Gx * im, ny = Gy * im;
       const T coef = K.sig[pr] * Akl * mag;
       txx += coef * (T(1) - nx * nx);
@@ -335,6 +338,7 @@ __device__ __forceinline__ void pair_stress(const T cc[3], const T g[3][2], T rh
       nrm[2 * pr + 1] = T(0);
     }
   }
+  return any;
 }
 
 // F_s = div T with Eq. (12) on the stress components.

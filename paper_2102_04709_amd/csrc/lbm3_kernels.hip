@@ -88,6 +88,7 @@ struct Smem {
                          // same LDS as the stress)
   T *PR;                 // ring 1, 4 planes: R_1, R_2 of the recolouring
   uint8_t *FL;           // ring 3: flags
+  int *any_stress;       // set in phase B when some pair normal of the tile + 2 rings is nonzero
 };
 
 template <typename T>
@@ -95,7 +96,7 @@ __host__ __device__ inline size_t smem_bytes(int TX, int TY) {
   const size_t n3 = (size_t)(TX + 6) * (TY + 6), n2 = (size_t)(TX + 4) * (TY + 4),
                n1 = (size_t)(TX + 2) * (TY + 2);
   const size_t shared = 3 * n2 > 9 * n1 ? 3 * n2 : 9 * n1;
-  return (3 * n3 + n2 + shared + 4 * n1) * sizeof(T) + ((n3 + 15) & ~(size_t)15);
+  return (3 * n3 + n2 + shared + 4 * n1) * sizeof(T) + ((n3 + 15) & ~(size_t)15) + 16;
 }
 
 template <typename T, int W1, int W3, int N1>
@@ -137,6 +138,7 @@ void step_fused(StepArgs<S, T> A) {
     L.PF = p; p += (3 * N2 > 9 * N1 ? 3 * N2 : 9 * N1);
     L.PR = p; p += 4 * N1;
     L.FL = reinterpret_cast<uint8_t *>(p);
+    L.any_stress = reinterpret_cast<int *>(L.FL + ((N3 + 15) & ~15));
   }
   constexpr bool FIELDS = OUT == OUT_FIELDS, ADJ = OUT == OUT_ADJ;
   const int tid = threadIdx.x;
@@ -154,6 +156,7 @@ void step_fused(StepArgs<S, T> A) {
     const bool inner = wk.kind & WK_INNER, plain = wk.kind & WK_PLAIN;
 
     // Phase A: C_k and rho on tile + 3 rings (with the wetting fill at the fill nodes).
+    if (tid == 0) *L.any_stress = 0;
     for (int q = tid; q < N3; q += NT) {
       const int lx = q % W3, ly = q / W3;
       const int64_t li = inner ? plane_index(x0 - 3 + lx, y0 - 3 + ly, D.pitch)
@@ -176,6 +179,7 @@ void step_fused(StepArgs<S, T> A) {
     __syncthreads();
 
     // Phase B: Eq. (12) gradients and the Eq. (10) stress on tile + 2 rings; recolouring vectors.
+    bool any_g = false;
     for (int q = tid; q < N2; q += NT) {
       const int lx = q % W2, ly = q / W2;
       const int p3 = (lx + 1) + (ly + 1) * W3;
@@ -191,7 +195,7 @@ void step_fused(StepArgs<S, T> A) {
       }
       const T cc[3] = {L.C0[p3], L.C1[p3], L.C2[p3]};
       T txx, txy, tyy, nrm[6];
-      pair_stress(cc, g, L.RH[q], K, eps_g, txx, txy, tyy, nrm);
+      any_g |= pair_stress(cc, g, L.RH[q], K, eps_g, txx, txy, tyy, nrm);
       L.Txx[q] = txx; L.Txy[q] = txy; L.Tyy[q] = tyy;
       // Eq. (13)-(15): the recolouring vectors of the fluid nodes of tile + 1 ring, from the
       // normals just formed (phase C needs only them, not the normals)
@@ -214,6 +218,7 @@ void step_fused(StepArgs<S, T> A) {
         }
       }
     }
+    if (any_g) *L.any_stress = 1;
     __syncthreads();
 
     // Phase C: force (all ring-1 nodes first: the populations then overwrite the stress),
@@ -230,12 +235,15 @@ void step_fused(StepArgs<S, T> A) {
       if (FIELDS && (gx >= D.nx || gy >= D.ny)) return false;
       return true;
     };
+    // Where no pair normal of the tile + 2 rings passed |G| > eps (the bulk of each fluid), every
+    // stress there is +0 and so is its divergence: the force loop is skipped, with the same result.
+    const bool any_stress = *L.any_stress != 0;
     T Fxs[IC], Fys[IC];
 #pragma unroll
     for (int it = 0; it < IC; ++it) {
       const int q = tid + it * NT;
       Fxs[it] = Fys[it] = T(0);
-      if (!active_c(q)) continue;
+      if (!any_stress || !active_c(q)) continue;
       const int lx = q % W1, ly = q / W1;
       const int p2 = (lx + 1) + (ly + 1) * W2;
       const int off2[9] = {0, 1, W2, -1, -W2, 1 + W2, -1 + W2, -1 - W2, 1 - W2};
