@@ -454,7 +454,9 @@ __device__ __forceinline__ void fluid_parts(const Acc &acc, int dx, int dy, int 
 }
 
 // Eq. (16) pull-streaming into a fluid node whose eight neighbours are fluid and whose links cross
-// no x boundary with a rule of its own: the same sums as stream_node without its branches.
+// no x boundary with a rule of its own: the same sums as stream_node without its branches.  The
+// partial densities end with + 0, which turns a sum of zeros of either sign into +0 (a fluid absent
+// from the whole neighbourhood), so that stream_plain_bulk below gives the same bits.
 template <typename T, class Acc>
 __device__ __forceinline__ void stream_plain(const Acc &acc, T fo[9], T &ra, T &rb, T &rc) {
   ra = rb = rc = T(0);
@@ -466,6 +468,24 @@ __device__ __forceinline__ void stream_plain(const Acc &acc, T fo[9], T &ra, T &
     fo[a] = acc.f(a, -ex, -ey);
     ra += c[0]; rb += c[1]; rc += c[2];
   }
+  ra = ra + T(0); rb = rb + T(0); rc = rc + T(0);
+}
+
+// stream_plain where every recolouring vector the node reads is zero (no pair normal in reach): each
+// term C_k (f' + w) + w e.R_k is then C_k (f' + w) rounded the same way, so the sums match
+// stream_plain bit for bit without reading R.
+template <typename T, class Acc>
+__device__ __forceinline__ void stream_plain_bulk(const Acc &acc, T fo[9], T &ra, T &rb, T &rc) {
+  ra = rb = rc = T(0);
+#pragma unroll
+  for (int a = 0; a < 9; ++a) {
+    const int ex = lat_ex(a), ey = lat_ey(a);
+    fo[a] = acc.f(a, -ex, -ey);
+    const T fv = fo[a] + wgt<T>(a);
+    const T c0 = acc.C(0, -ex, -ey) * fv, c1 = acc.C(1, -ex, -ey) * fv, c2 = acc.C(2, -ex, -ey) * fv;
+    ra += c0; rb += c1; rc += c2;
+  }
+  ra = ra + T(0); rb = rb + T(0); rc = rc + T(0);
 }
 
 // Eq. (16) pull-streaming into one fluid node (gx, gy) from the post-collision data around it,
@@ -549,6 +569,7 @@ __device__ __forceinline__ void stream_node(const Acc &acc, int gx, const Domain
       fo[7] = ft[7] - wgt<T>(7);
     }
   }
+  ra = ra + T(0); rb = rb + T(0); rc = rc + T(0);  // +0 for a sum of zeros, as in stream_plain
 }
 
 }  // namespace lbm3

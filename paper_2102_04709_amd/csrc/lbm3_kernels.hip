@@ -357,8 +357,13 @@ void step_fused(StepArgs<S, T> A) {
       if (fl & FL_SOLID) continue;  // solid slots keep their constant contents
       TileAcc<T, W1, W3, N1> acc{L, p1, p3};
       T fo[9], ra, rb, rc;
-      if (plain) stream_plain<T>(acc, fo, ra, rb, rc);
-      else stream_node<T>(acc, gx, D, K, (fl & FL_CURVED) ? A.ibb + ibm[q] : nullptr, fo, ra, rb, rc);
+      if (plain) {
+        // no pair normal in the tile + 2 rings: every recolouring vector streaming reads is zero
+        if (any_stress) stream_plain<T>(acc, fo, ra, rb, rc);
+        else stream_plain_bulk<T>(acc, fo, ra, rb, rc);
+      } else {
+        stream_node<T>(acc, gx, D, K, (fl & FL_CURVED) ? A.ibb + ibm[q] : nullptr, fo, ra, rb, rc);
+      }
       // Non-temporal stores where a tile row covers whole 128-byte lines of a plane; narrower rows
       // share lines with the neighbouring tile, which the L2 then merges before writing back.
       if constexpr (TX * sizeof(S) >= 128) {
