@@ -89,6 +89,7 @@ struct Smem {
   T *PR;                 // ring 1, 4 planes: R_1, R_2 of the recolouring
   uint8_t *FL;           // ring 3: flags
   int *any_stress;       // set in phase B when some pair normal of the tile + 2 rings is nonzero
+  int *present;          // phase A: bit k set when some C_k of the tile + 3 rings is nonzero
 };
 
 template <typename T>
@@ -139,10 +140,17 @@ void step_fused(StepArgs<S, T> A) {
     L.PR = p; p += 4 * N1;
     L.FL = reinterpret_cast<uint8_t *>(p);
     L.any_stress = reinterpret_cast<int *>(L.FL + ((N3 + 15) & ~15));
+    L.present = L.any_stress + 1;
   }
   constexpr bool FIELDS = OUT == OUT_FIELDS, ADJ = OUT == OUT_ADJ;
+  // single-fluid tiles skip phase B in the streaming step; not in the 16-wide tiles, where the
+  // test's registers cost a spill in the collision (and tiles of small, latency-bound domains
+  // gain little from it)
+  constexpr bool SKIP1 = !FIELDS && !ADJ && TX >= 32;
   const int tid = threadIdx.x;
   const T eps_g = A.eps_g;
+  if (tid == 0) *L.present = 0;  // (phase C clears it again after each work item's phase B reads it)
+  __syncthreads();
 
   for (int wi = A.work_begin + first_item(A.remap); wi < A.work_end; wi += A.remap ? A.work_end : gridDim.x) {
     const WorkItem wk = A.work[wi];
@@ -157,6 +165,7 @@ void step_fused(StepArgs<S, T> A) {
 
     // Phase A: C_k and rho on tile + 3 rings (with the wetting fill at the fill nodes).
     if (tid == 0) *L.any_stress = 0;
+    int fluids = 0;  // bit k: some C_k this thread formed is nonzero
     for (int q = tid; q < N3; q += NT) {
       const int lx = q % W3, ly = q / W3;
       const int64_t li = inner ? plane_index(x0 - 3 + lx, y0 - 3 + ly, D.pitch)
@@ -166,6 +175,7 @@ void step_fused(StepArgs<S, T> A) {
       node_composition<T>(fl, *elem32(Rin, li), *elem32(Rin + P, li), *elem32(Rin + 2 * P, li), A.fillC, v);
       L.FL[q] = fl;
       L.C0[q] = v[0]; L.C1[q] = v[1]; L.C2[q] = v[2];
+      if (SKIP1) fluids |= (v[0] != T(0) ? 1 : 0) | (v[1] != T(0) ? 2 : 0) | (v[2] != T(0) ? 4 : 0);
       if (lx >= 1 && lx <= W3 - 2 && ly >= 1 && ly <= H3 - 2) L.RH[(lx - 1) + (ly - 1) * W2] = v[3];
       if (ADJ) {  // C_k and rho at the tile's in-grid positions
         const int gx = x0 - 3 + lx, gy = y0 - 3 + ly;
@@ -176,11 +186,21 @@ void step_fused(StepArgs<S, T> A) {
         }
       }
     }
+    if (SKIP1) {  // the fluids present in the tile + 3 rings: one LDS OR per wave
+      const int wf = (__ballot(fluids & 1) ? 1 : 0) | (__ballot(fluids & 2) ? 2 : 0) | (__ballot(fluids & 4) ? 4 : 0);
+      if ((tid & 63) == 0 && wf) atomicOr(L.present, wf);
+    }
     __syncthreads();
 
     // Phase B: Eq. (12) gradients and the Eq. (10) stress on tile + 2 rings; recolouring vectors.
+    // A plain tile whose tile + 3 rings hold a single fluid (every other C_k exactly zero) has
+    // G_kl = C_l grad C_k - C_k grad C_l = 0 for every pair, so no pair passes |G| > eps: phase B
+    // would leave the stress +0 and the normals zero, which the force loop and the plain streaming
+    // of such a tile do not read (they are skipped below), so it is skipped as well.
+    const int fluids_here = __builtin_amdgcn_readfirstlane(*L.present);  // (uniform: a scalar)
+    const bool single_fluid = SKIP1 && plain && (fluids_here & (fluids_here - 1)) == 0;
     bool any_g = false;
-    for (int q = tid; q < N2; q += NT) {
+    for (int q = single_fluid ? N2 : tid; q < N2; q += NT) {
       const int lx = q % W2, ly = q / W2;
       const int p3 = (lx + 1) + (ly + 1) * W3;
       const int off[9] = {0, 1, W3, -1, -W3, 1 + W3, -1 + W3, -1 - W3, 1 - W3};
@@ -195,7 +215,8 @@ void step_fused(StepArgs<S, T> A) {
       }
       const T cc[3] = {L.C0[p3], L.C1[p3], L.C2[p3]};
       T txx, txy, tyy, nrm[6];
-      any_g |= pair_stress(cc, g, L.RH[q], K, eps_g, txx, txy, tyy, nrm);
+      const bool node_g = pair_stress(cc, g, L.RH[q], K, eps_g, txx, txy, tyy, nrm);
+      any_g |= node_g;
       L.Txx[q] = txx; L.Txy[q] = txy; L.Tyy[q] = tyy;
       // Eq. (13)-(15): the recolouring vectors of the fluid nodes of tile + 1 ring, from the
       // normals just formed (phase C needs only them, not the normals)
@@ -203,8 +224,10 @@ void step_fused(StepArgs<S, T> A) {
         if (!ADJ) {  // (the adjoint's tiles do not stream)
           const int p1 = (lx - 1) + (ly - 1) * W1;
           const T rt = L.RH[q];
-          T Rv[4];
-          recolour_R(cc[0] * rt, cc[1] * rt, cc[2] * rt, rt, nrm, K, Rv);
+          // with all normals zero the vectors are zeros (of either sign), which the streaming
+          // sums treat exactly as +0: they are written as +0 without being formed
+          T Rv[4] = {T(0), T(0), T(0), T(0)};
+          if (node_g) recolour_R(cc[0] * rt, cc[1] * rt, cc[2] * rt, rt, nrm, K, Rv);
 #pragma unroll
           for (int c = 0; c < 4; ++c) L.PR[c * N1 + p1] = Rv[c];
         }
@@ -220,6 +243,7 @@ void step_fused(StepArgs<S, T> A) {
     }
     if (any_g) *L.any_stress = 1;
     __syncthreads();
+    if (tid == 0) *L.present = 0;  // every thread read it before the barrier above
 
     // Phase C: force (all ring-1 nodes first: the populations then overwrite the stress),
     // velocity and MRT collision on tile + 1 ring.
@@ -237,7 +261,7 @@ void step_fused(StepArgs<S, T> A) {
     };
     // Where no pair normal of the tile + 2 rings passed |G| > eps (the bulk of each fluid), every
     // stress there is +0 and so is its divergence: the force loop is skipped, with the same result.
-    const bool any_stress = *L.any_stress != 0;
+    const bool any_stress = __builtin_amdgcn_readfirstlane(*L.any_stress) != 0;
     T Fxs[IC], Fys[IC];
 #pragma unroll
     for (int it = 0; it < IC; ++it) {
