@@ -183,12 +183,12 @@ void fill_candidates(const DomainDev &D, const uint8_t *flags, const FillNode &f
     for (int c = 0; c < kFillCands; ++c) {
       const double tk = std::min(std::max(ang[line >> 1][c], 5.0 * PI / 180.0), 175.0 * PI / 180.0);
       const double phi = std::fabs(0.5 * PI - tk);
-      double sp, cp;
-      sincos_quadrant(phi, sp, cp);
-      if (line & 1) sp = -sp;
-      const double nx = fn.nx, ny = fn.ny, tx = -ny, ty = nx;
-      const LineHit h = march_line(fn.i, fn.j, cp * nx + sp * tx, cp * ny + sp * ty, fluid_at);
-      out[line * kFillCands + c] = h.ok ? FillCand{wrapped(h.i0, h.j0), wrapped(h.i1, h.j1), h.w} : FillCand{-1, -1, 0.0};
+      FillCand &o = out[line * kFillCands + c];
+      double lo, hi;
+      int hk[2];
+      const LineHit h = line_angle_range(fn.i, fn.j, fn.nx, fn.ny, (line & 1) ? -1.0 : 1.0, phi, fluid_at, lo, hi, hk);
+      o = h.ok ? FillCand{wrapped(h.i0, h.j0), wrapped(h.i1, h.j1), h.w, lo, hi, hk[0], hk[1]}
+               : FillCand{-1, -1, 0.0, 1.0, 0.0, 1, 1};
     }
 }
 

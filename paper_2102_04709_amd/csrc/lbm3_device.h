@@ -131,8 +131,10 @@ __device__ __forceinline__ double cfrac_at(const T *r, int64_t P, int64_t q, int
 // right before the march (it places the node's far mask at `far_rows`, a work-group barrier).
 // cand (may be null): the line's crossings for the pure-composition angles of its fluid; when C at
 // D0 leaves Eq. (21) one of them (the other two fluids' weights below 1e-15 of their sum, or both
-// absent) the line takes that crossing instead of marching.  The densities at the first candidate's
-// nodes (the angle against fluid 3, the usual ambient) are loaded together with those of D0.
+// absent) the line takes that crossing instead of marching; a line whose angle lies in a
+// candidate's range (FillCand) starts its march at the candidate's crossing.  The densities at the
+// first candidate's nodes (the angle against fluid 3, the usual ambient) are loaded together with
+// those of D0, and used wherever the line's crossing has those nodes.
 template <typename T, class Stage>
 __device__ __forceinline__ void fill_lanes(const FillNode &fn, const DomainDev &D, const uint8_t *flags,
                                            const T *r, const uint32_t *far_rows, const Stage &stage, int line,
@@ -157,8 +159,9 @@ __device__ __forceinline__ void fill_lanes(const FillNode &fn, const DomainDev &
   };
   const double PI = 3.14159265358979323846;
   const int k = line >> 1;
-  // the first candidate crossing's densities, loaded beside those of D0
-  const FillCand c0 = cand ? cand[0] : FillCand{-1, -1, 0.0};
+  // the line's first candidate crossing (the angle against fluid 3, the usual ambient) and its
+  // densities, beside those of D0 (the other two candidates load where they are needed)
+  const FillCand c0 = cand ? cand[0] : FillCand{-1, -1, 0.0, 1.0, 0.0, 1, 1};
   T rc0[2][3];
   {
     const int64_t qa = c0.a >= 0 ? c0.a : fn.d0a, qb = c0.a >= 0 ? c0.b : fn.d0a;
@@ -192,32 +195,43 @@ __device__ __forceinline__ void fill_lanes(const FillNode &fn, const DomainDev &
   double v = 0.0;
   int ok = 0;
   stage();
-  if (active && pick == 0) {  // the precomputed crossing whose densities are in
-    if (c0.a >= 0) {
-      const double ca = (double)rc0[0][k] / ((double)rc0[0][0] + (double)rc0[0][1] + (double)rc0[0][2]);
-      const double cb = (double)rc0[1][k] / ((double)rc0[1][0] + (double)rc0[1][1] + (double)rc0[1][2]);
-      v = ca + c0.w * (cb - ca);
-      ok = 1;
-    }
-  } else if (active && pick > 0) {  // another precomputed crossing
-    const FillCand h = cand[pick];
-    if (h.a >= 0) {
-      const double ca = cfrac_at(r, P, h.a, k), cb = cfrac_at(r, P, h.b, k);
-      v = ca + h.w * (cb - ca);
-      ok = 1;
-    }
+  // the crossing's interpolation nodes and weight (qa < 0: none)
+  int64_t qa = -1, qb = -1;
+  double w_hit = 0.0;
+  if (active && pick >= 0) {  // a precomputed crossing
+    const FillCand h = pick == 0 ? c0 : cand[pick];
+    if (h.a >= 0) { qa = h.a; qb = h.b; w_hit = h.w; }
   } else if (active) {
     const double phi = fabs(0.5 * PI - tk);
     double sp, cp;
     sincos_quadrant(phi, sp, cp);
     if (line & 1) sp = -sp;
     const double nx = fn.nx, ny = fn.ny, tx = -ny, ty = nx;
-    const LineHit h = march_line_masked(fn.i, fn.j, cp * nx + sp * tx, cp * ny + sp * ty, fn.mask, far_rows, fluid_at);
-    if (h.ok) {
-      const double ca = cfrac_at(r, P, node_q(h.i0, h.j0), k), cb = cfrac_at(r, P, node_q(h.i1, h.j1), k);
-      v = ca + h.w * (cb - ca);
-      ok = 1;
+    // within a candidate's angle range the march meets its hit at the candidate's crossing: it
+    // starts there (the usual case of a composition with traces of a third fluid)
+    int kx = 1, ky = 1;
+    if (phi >= c0.phi_lo && phi <= c0.phi_hi) {
+      kx = c0.kx; ky = c0.ky;
+    } else if (cand) {
+#pragma unroll
+      for (int c = 1; c < kFillCands; ++c) {
+        const FillCand h = cand[c];
+        if (phi >= h.phi_lo && phi <= h.phi_hi) { kx = h.kx; ky = h.ky; }
+      }
     }
+    const LineHit h = march_line_masked(fn.i, fn.j, cp * nx + sp * tx, cp * ny + sp * ty, fn.mask, far_rows,
+                                        fluid_at, kx, ky);
+    if (h.ok) { qa = node_q(h.i0, h.j0); qb = node_q(h.i1, h.j1); w_hit = h.w; }
+  }
+  if (qa >= 0 && c0.a == qa && c0.b == qb) {  // the first candidate's nodes: densities in
+    const double ca = (double)rc0[0][k] / ((double)rc0[0][0] + (double)rc0[0][1] + (double)rc0[0][2]);
+    const double cb = (double)rc0[1][k] / ((double)rc0[1][0] + (double)rc0[1][1] + (double)rc0[1][2]);
+    v = ca + w_hit * (cb - ca);
+    ok = 1;
+  } else if (qa >= 0) {
+    const double ca = cfrac_at(r, P, qa, k), cb = cfrac_at(r, P, qb, k);
+    v = ca + w_hit * (cb - ca);
+    ok = 1;
   }
   const double vo = __shfl_xor(v, 1);
   const int oko = __shfl_xor(ok, 1);

@@ -15,6 +15,9 @@
 
 #include <stdint.h>
 
+#include <cmath>
+#include <vector>
+
 #ifndef __HIPCC__
 #define __host__
 #define __device__
@@ -96,9 +99,16 @@ struct FillNode {
 // of the pair when neither of the other two is present): the two interpolation nodes as plane
 // indices (a < 0: the line reaches no fluid) and the weight, C(D) = C(a) + w (C(b) - C(a)).
 // Formed once in FP64 at set-up (and when the angles change) with the march of the fill.
+// phi_lo..phi_hi: the line angles phi = |pi/2 - theta| around the candidate's over which the
+// march crosses the same grid lines in the same order and classifies them alike up to its hit
+// (bounded by the angles of rays through lattice nodes and of axis-parallel rays, with a margin;
+// phi_lo > phi_hi: none), so a line whose angle lies there has its hit at the same crossing:
+// the march may start there, at crossing counters kx, ky, and reach the same result.
 struct FillCand {
   int32_t a, b;
   double w;
+  double phi_lo, phi_hi;
+  int32_t kx, ky;
 };
 constexpr int kFillCands = 3;  // candidate angles per fluid
 
@@ -155,9 +165,10 @@ struct LineHit {
 
 // kx, ky: the indices of the next vertical and horizontal crossings to visit (1, 1 from the
 // node; a march that resumes another one's passes that march's state).
+// hit_k (may be null): receives the counters kx, ky with which the hit crossing was reached.
 template <class FluidAt>
 __host__ __device__ inline LineHit march_line(int pi, int pj, double dx, double dy,
-                                              const FluidAt &fluid, int kx = 1, int ky = 1) {
+                                              const FluidAt &fluid, int kx = 1, int ky = 1, int *hit_k = nullptr) {
   LineHit h;
   h.ok = 0;
   h.i0 = h.j0 = h.i1 = h.j1 = 0;
@@ -167,6 +178,7 @@ __host__ __device__ inline LineHit march_line(int pi, int pj, double dx, double 
   const double ax = dx < 0 ? -dx : dx, ay = dy < 0 ? -dy : dy;
   const double iax = sx ? 1.0 / ax : 0.0, iay = sy ? 1.0 / ay : 0.0;
   for (int guard = 0; guard < 256; ++guard) {
+    if (hit_k) { hit_k[0] = kx; hit_k[1] = ky; }
     const double tx = sx ? (double)kx * iax : 1e300;  // t of the next vertical line
     const double ty = sy ? (double)ky * iay : 1e300;  // t of the next horizontal line
     const double t = tx < ty ? tx : ty;
@@ -271,12 +283,13 @@ constexpr int kFarR = 12, kFarW = 2 * kFarR + 1;
 
 template <class FluidAt>
 __host__ __device__ inline LineHit march_line_masked(int pi, int pj, double dx, double dy, const FluidMask &mask,
-                                                     const uint32_t *far_rows, const FluidAt &fluid) {
+                                                     const uint32_t *far_rows, const FluidAt &fluid, int kx = 1,
+                                                     int ky = 1) {
   auto near_test = [&](int a, int b) { return mask.fluid(a, b); };
   auto far_test = [&](int a, int b) { return ((far_rows[b + kFarR] >> (a + kFarR)) & 1u) != 0; };
   auto general = [&](int kx, int ky) { return march_line(pi, pj, dx, dy, fluid, kx, ky); };
   auto far = [&](int kx, int ky) { return march_line_block<kFarR>(pi, pj, dx, dy, far_test, general, kx, ky); };
-  return march_line_block<kMaskR>(pi, pj, dx, dy, near_test, far);
+  return march_line_block<kMaskR>(pi, pj, dx, dy, near_test, far, kx, ky);
 }
 
 // sin and cos of an angle in [0, pi/2] in FP64 (the wetting fill's line angle phi), to a few
@@ -318,6 +331,67 @@ __host__ __device__ inline void sincos_quadrant(double phi, double &sn, double &
   const double c = 1.0 + x2 * pc;
   sn = comp ? c : s;
   cs = comp ? s : c;
+}
+
+// Host: the march of the fill's line at angle phi on side s (direction cos(phi) n + s sin(phi) t,
+// t = (-n_y, n_x)), and the range lo..hi of angles around phi over which the march meets its hit
+// at the same crossing, reached with counters hk (lo > hi: none; also when the line has no hit).
+// The march's crossings, their order and their node / segment classification change only near the
+// angles of rays through lattice nodes (up to the hit's distance, plus a margin) and of rays
+// parallel to an axis; between two such angles, farther from both than the node tolerance's
+// angular width (below 1e-9 for nodes at distance 1 or more), they are fixed.  When phi itself is
+// at such an angle (a ray through a node), the range is the +-2e-11 over which every crossing keeps
+// its class.  The range is kept only if the march at its ends and midpoints agrees.
+template <class FluidAt>
+inline LineHit line_angle_range(int pi, int pj, double nx, double ny, double s, double phi, const FluidAt &fluid,
+                                double &lo, double &hi, int hk[2]) {
+  const double half_pi = 1.5707963267948966, tx = -ny, ty = nx;
+  auto march_at = [&](double a, int *k) {
+    double sp, cp;
+    sincos_quadrant(a, sp, cp);
+    sp *= s;
+    return march_line(pi, pj, cp * nx + sp * tx, cp * ny + sp * ty, fluid, 1, 1, k);
+  };
+  hk[0] = hk[1] = 1;
+  lo = 1.0;
+  hi = 0.0;
+  const LineHit h = march_at(phi, hk);
+  if (!h.ok) return h;
+  const double reach = std::hypot(0.5 * (h.i0 + h.i1) - pi, 0.5 * (h.j0 + h.j1) - pj) + 2.0;
+  const int R = (int)std::ceil(reach);
+  std::vector<double> brk;
+  for (int v = -R; v <= R; ++v)
+    for (int u = -R; u <= R; ++u) {
+      if ((u == 0 && v == 0) || u * u + v * v > R * R) continue;
+      const double a = std::atan2(s * (u * tx + v * ty), u * nx + v * ny);
+      if (a >= -1e-6 && a <= half_pi + 1e-6) brk.push_back(a);
+    }
+  for (const double a : {std::atan2(-nx, s * tx), std::atan2(-ny, s * ty), std::atan2(nx, -s * tx), std::atan2(ny, -s * ty)})
+    if (a >= -1e-6 && a <= half_pi + 1e-6) brk.push_back(a);
+  const double m = 1e-9;
+  double l = -1.0, u = 10.0;
+  bool on_break = false;
+  for (const double a : brk) {
+    if (std::fabs(a - phi) <= m) on_break = true;
+    else if (a < phi) l = std::fmax(l, a + m);
+    else u = std::fmin(u, a - m);
+  }
+  if (on_break) {
+    l = phi - 2e-11;
+    u = phi + 2e-11;
+  }
+  l = std::fmax(l, 0.0);
+  u = std::fmin(u, half_pi);
+  if (!(l <= phi && phi <= u)) return h;
+  for (const double a : {l, 0.5 * (l + phi), 0.5 * (phi + u), u}) {
+    int k2[2];
+    const LineHit g = march_at(a, k2);
+    if (!(g.ok && g.i0 == h.i0 && g.j0 == h.j0 && g.i1 == h.i1 && g.j1 == h.j1 && k2[0] == hk[0] && k2[1] == hk[1]))
+      return h;
+  }
+  lo = l;
+  hi = u;
+  return h;
 }
 
 }  // namespace lbm3

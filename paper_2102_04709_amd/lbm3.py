@@ -70,6 +70,11 @@ def library() -> C.CDLL:
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+        # torch first: its wheel carries its own HIP and HSA runtimes, and the library must bind to
+        # those (the ones that own the device memory and streams passed to it).  Loaded before
+        # torch, it would bring up the system runtimes, and the second pair loaded with torch then
+        # finds no device.
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         vp, i32, dp, szp = C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_size_t)
         dom_p, opt_p = C.POINTER(lbm3_domain), C.POINTER(lbm3_options)

@@ -3,7 +3,9 @@
 // must give exactly march_line's hit (same nodes, bit-identical weight)
 // for random fluid fields and directions, including lattice and rational-slope directions that
 // pass through nodes; sincos_quadrant must agree with long-double sin/cos to 1 ulp on the angle
-// range of Eq. (22)'s lines, [0, 85] degrees.
+// range of Eq. (22)'s lines, [0, 85] degrees; and a candidate's angle range (line_angle_range) must
+// hold only angles at which the march started at the candidate's crossing counters gives the full
+// march's hit.
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -21,7 +23,7 @@ int main(int argc, char **argv) {
   std::mt19937_64 g(2102);
   std::uniform_real_distribution<double> U(0.0, 1.0);
   static int fl[41][41];
-  long bad = 0, hits = 0;
+  long bad = 0, hits = 0, ranges = 0, bad_range = 0;
   for (long trial = 0; trial < trials; ++trial) {
     const double p = 0.2 + 0.75 * U(g);
     const int shape = trial % 4;
@@ -66,6 +68,41 @@ int main(int argc, char **argv) {
     if (a.ok != b.ok || (a.ok && (a.i0 != b.i0 || a.j0 != b.j0 || a.i1 != b.i1 || a.j1 != b.j1 || a.w != b.w))) {
       if (++bad <= 5) std::printf("march mismatch, trial %ld angle %.17g\n", trial, ang);
     }
+    // A candidate's angle range: at any angle in it, the masked march started at the candidate's
+    // counters gives exactly the full march's hit.  Normals at random and lattice angles, the
+    // candidate at a random angle, at 0 (along the normal) or on a ray through a node.
+    if (trial % 4 == 0) {
+      double al = U(g) * 6.283185307179586;
+      if (trial % 3 == 0) al = (int)(U(g) * 8) * 0.7853981633974483;
+      const double nx = std::cos(al), ny = std::sin(al), s = U(g) < 0.5 ? 1.0 : -1.0;
+      double phi = U(g) * 1.4835298641951802;
+      if (trial % 5 == 0) phi = 0.0;
+      if (trial % 5 == 1) {  // a ray through a nearby node, when one lies in the angle range
+        const int u = (int)(U(g) * 9) - 4, v = (int)(U(g) * 9) - 4;
+        const double t = std::atan2(s * (u * -ny + v * nx), u * nx + v * ny);
+        if ((u || v) && t >= 0.0 && t <= 1.4835298641951802) phi = t;
+      }
+      double lo, hi;
+      int hk[2];
+      const LineHit c = line_angle_range(pi, pj, nx, ny, s, phi, fluid, lo, hi, hk);
+      if (lo <= hi) {
+        ++ranges;
+        for (int q = 0; q < 8; ++q) {
+          const double f = q == 0 ? lo : (q == 1 ? hi : (q == 2 ? phi : lo + (hi - lo) * U(g)));
+          double sp, cp;
+          sincos_quadrant(f, sp, cp);
+          sp *= s;
+          const double ex = cp * nx + sp * -ny, ey = cp * ny + sp * nx;
+          const LineHit full = march_line(pi, pj, ex, ey, fluid);
+          const LineHit from = march_line_masked(pi, pj, ex, ey, mask, far, fluid, hk[0], hk[1]);
+          const bool same = full.ok == from.ok && full.ok && full.i0 == from.i0 && full.j0 == from.j0 &&
+                            full.i1 == from.i1 && full.j1 == from.j1 && full.w == from.w && full.i0 == c.i0 &&
+                            full.j0 == c.j0 && full.i1 == c.i1 && full.j1 == c.j1;
+          if (!same && ++bad_range <= 5)
+            std::printf("range mismatch, trial %ld phi %.17g in [%.17g, %.17g] at %.17g\n", trial, phi, lo, hi, f);
+        }
+      }
+    }
   }
   double es = 0.0, ec = 0.0;
   const long n = 1000000;
@@ -76,6 +113,7 @@ int main(int argc, char **argv) {
     es = std::fmax(es, ulps(s, (double)sinl((long double)phi)));
     ec = std::fmax(ec, ulps(c, (double)cosl((long double)phi)));
   }
-  std::printf("trials %ld hits %ld march mismatches %ld; sincos max ulp %.2f %.2f\n", trials, hits, bad, es, ec);
-  return (bad != 0 || es > 1.0 || ec > 1.0) ? 1 : 0;
+  std::printf("trials %ld hits %ld march mismatches %ld; angle ranges %ld, mismatches %ld; sincos max ulp %.2f %.2f\n",
+              trials, hits, bad, ranges, bad_range, es, ec);
+  return (bad != 0 || bad_range != 0 || ranges < trials / 20 || es > 1.0 || ec > 1.0) ? 1 : 0;
 }

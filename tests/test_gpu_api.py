@@ -71,3 +71,25 @@ def test_non_finite_density_is_reported():
     torch.cuda.synchronize()
     assert not bool(torch.isfinite(m).all())
     sim.close()
+
+
+def test_library_loaded_before_torch():
+    """A process that loads the library before anything imports torch still runs a step: the
+    loader brings torch's HIP runtime up first, so the library shares it (with the system runtime
+    loaded first, the runtime that comes with torch later finds no device)."""
+    _mods()
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_2102_04709_amd import lbm3, workloads as W\n"
+            "assert 'torch' not in sys.modules\n"
+            "lbm3.library()\n"
+            "sim = lbm3.Simulation(W.random_mixture(64, 48, seed=1), precision='f32')\n"
+            "sim.step(2)\n"
+            "print('mass', float(sim.mass().sum()))\n" % root)
+    print("library before torch: subprocess", flush=True)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "mass" in r.stdout
