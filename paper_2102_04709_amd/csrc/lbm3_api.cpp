@@ -19,6 +19,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "lbm3.h"
@@ -159,7 +160,22 @@ void param_jacobian(const double *theta_deg, const double *sigma, double J[9][5]
 // the angles Eq. (21) gives when at most two fluids are present at D0: fluid 1 theta13, theta12 or
 // their mean, fluid 2 theta23, theta21 = pi - theta12 or their mean; with the fill's own angle
 // clamp, sine and cosine and march, in FP64.  flags: the domain's flag plane.
-void fill_candidates(const DomainDev &D, const uint8_t *flags, const FillNode &fn, FillCand *out) {
+// The angle ranges (and crossing counters) of a fill node's candidates depend only on its normal,
+// the candidate angles and the fluid flags its marches test: when every candidate's march stays in
+// the node's 11 x 11 block, on the node's fluid mask (FillNode::mask), so nodes with the same
+// mask and normal (flat walls) share them.
+constexpr int kRangeReach = 8;
+struct CandRangeCache {
+  struct Entry {
+    int32_t rel[4 * kFillCands][4];  // the crossing's nodes relative to the fill node
+    double lo[4 * kFillCands], hi[4 * kFillCands];
+    int32_t kx[4 * kFillCands], ky[4 * kFillCands];
+  };
+  std::unordered_map<std::string, Entry> map;
+};
+
+void fill_candidates(const DomainDev &D, const uint8_t *flags, const FillNode &fn, FillCand *out,
+                     CandRangeCache *cache) {
   const double PI = 3.14159265358979323846;
   const bool zh = D.bcx == BCX_ZOUHE;
   auto fluid_at = [&](int i, int j) -> bool {
@@ -179,17 +195,89 @@ void fill_candidates(const DomainDev &D, const uint8_t *flags, const FillNode &f
   };
   const double th21 = PI - D.th12;
   const double ang[2][kFillCands] = {{D.th13, D.th12, 0.5 * (D.th13 + D.th12)}, {D.th23, th21, 0.5 * (D.th23 + th21)}};
+  auto phi_of = [&](int line, int c) {
+    const double tk = std::min(std::max(ang[line >> 1][c], 5.0 * PI / 180.0), 175.0 * PI / 180.0);
+    return std::fabs(0.5 * PI - tk);
+  };
+  // Angle ranges only for crossings within a reach of kRangeReach (nearly all: the lines that go
+  // farther are few, and their breakpoint sets large), from one sorted set of breakpoints per side
+  // (lines 0, 2: +t; 1, 3: -t) for the farthest of those crossings.
+  LineHit hit[4][kFillCands];
+  int R[2] = {0, 0};
+  bool in_block = true;
   for (int line = 0; line < 4; ++line)
     for (int c = 0; c < kFillCands; ++c) {
-      const double tk = std::min(std::max(ang[line >> 1][c], 5.0 * PI / 180.0), 175.0 * PI / 180.0);
-      const double phi = std::fabs(0.5 * PI - tk);
+      double sp, cp;
+      sincos_quadrant(phi_of(line, c), sp, cp);
+      if (line & 1) sp = -sp;
+      const double tx = -fn.ny, ty = fn.nx;
+      // (the block march: the same hit as march_line's; it reports a line that leaves the block)
+      auto leaves = [&](int kx, int ky) {
+        in_block = false;
+        return march_line(fn.i, fn.j, cp * fn.nx + sp * tx, cp * fn.ny + sp * ty, fluid_at, kx, ky);
+      };
+      auto near_test = [&](int a, int b) { return fn.mask.fluid(a, b); };
+      hit[line][c] = march_line_block<kMaskR>(fn.i, fn.j, cp * fn.nx + sp * tx, cp * fn.ny + sp * ty, near_test, leaves);
+      const int r = hit[line][c].ok ? line_reach(fn.i, fn.j, hit[line][c]) : kRangeReach + 1;
+      if (r <= kRangeReach) R[line & 1] = std::max(R[line & 1], r);
+    }
+  for (int line = 0; line < 4; ++line)
+    for (int c = 0; c < kFillCands; ++c) {
+      const LineHit &h = hit[line][c];
+      out[line * kFillCands + c] = h.ok ? FillCand{wrapped(h.i0, h.j0), wrapped(h.i1, h.j1), h.w, 1.0, 0.0, 1, 1}
+                                        : FillCand{-1, -1, 0.0, 1.0, 0.0, 1, 1};
+    }
+  bool all_near = in_block;
+  for (int line = 0; line < 4; ++line)
+    for (int c = 0; c < kFillCands; ++c)
+      all_near = all_near && hit[line][c].ok && line_reach(fn.i, fn.j, hit[line][c]) <= kRangeReach;
+  std::string key;
+  if (cache && all_near) {
+    const double head[5] = {fn.nx, fn.ny, D.th13, D.th12, D.th23};
+    key.assign(reinterpret_cast<const char *>(head), sizeof head);
+    key.append(reinterpret_cast<const char *>(fn.mask.w), sizeof fn.mask.w);
+    const auto it = cache->map.find(key);
+    if (it != cache->map.end()) {
+      const CandRangeCache::Entry &e = it->second;
+      for (int q = 0; q < 4 * kFillCands; ++q) {
+        const LineHit &h = hit[q / kFillCands][q % kFillCands];
+        if (e.rel[q][0] != h.i0 - fn.i || e.rel[q][1] != h.j0 - fn.j || e.rel[q][2] != h.i1 - fn.i ||
+            e.rel[q][3] != h.j1 - fn.j)
+          continue;  // (cannot differ: the same surroundings give the same crossings)
+        out[q].phi_lo = e.lo[q];
+        out[q].phi_hi = e.hi[q];
+        out[q].kx = e.kx[q];
+        out[q].ky = e.ky[q];
+      }
+      return;
+    }
+  }
+  const std::vector<double> brk[2] = {line_breakpoints(fn.nx, fn.ny, 1.0, R[0]), line_breakpoints(fn.nx, fn.ny, -1.0, R[1])};
+  for (int line = 0; line < 4; ++line)
+    for (int c = 0; c < kFillCands; ++c) {
       FillCand &o = out[line * kFillCands + c];
+      const LineHit &h = hit[line][c];
+      if (!h.ok || line_reach(fn.i, fn.j, h) > kRangeReach) continue;
       double lo, hi;
       int hk[2];
-      const LineHit h = line_angle_range(fn.i, fn.j, fn.nx, fn.ny, (line & 1) ? -1.0 : 1.0, phi, fluid_at, lo, hi, hk);
-      o = h.ok ? FillCand{wrapped(h.i0, h.j0), wrapped(h.i1, h.j1), h.w, lo, hi, hk[0], hk[1]}
-               : FillCand{-1, -1, 0.0, 1.0, 0.0, 1, 1};
+      const LineHit g = line_angle_range(fn.i, fn.j, fn.nx, fn.ny, (line & 1) ? -1.0 : 1.0, phi_of(line, c), fluid_at,
+                                         lo, hi, hk, &brk[line & 1], R[line & 1]);
+      if (g.ok && g.i0 == h.i0 && g.j0 == h.j0 && g.i1 == h.i1 && g.j1 == h.j1) {
+        o.phi_lo = lo;
+        o.phi_hi = hi;
+        o.kx = hk[0];
+        o.ky = hk[1];
+      }
     }
+  if (cache && all_near) {
+    CandRangeCache::Entry e;
+    for (int q = 0; q < 4 * kFillCands; ++q) {
+      const LineHit &h = hit[q / kFillCands][q % kFillCands];
+      e.rel[q][0] = h.i0 - fn.i; e.rel[q][1] = h.j0 - fn.j; e.rel[q][2] = h.i1 - fn.i; e.rel[q][3] = h.j1 - fn.j;
+      e.lo[q] = out[q].phi_lo; e.hi[q] = out[q].phi_hi; e.kx[q] = out[q].kx; e.ky[q] = out[q].ky;
+    }
+    cache->map.emplace(std::move(key), e);
+  }
 }
 
 bool validate_and_build(const lbm3_domain &d, int dom, double beta0, DomHost &H, std::string &err) {
@@ -305,6 +393,7 @@ bool validate_and_build(const lbm3_domain &d, int dom, double beta0, DomHost &H,
         }
     }
   // Fill list with Eq. (19)-(20) normals.
+  CandRangeCache ranges;  // (shared by the domain's fill nodes)
   for (int pass = 1; pass <= 2; ++pass)
     for (int j = jlo; j <= jhi; ++j)
       for (int i = 0; i < nx; ++i) {
@@ -357,7 +446,7 @@ bool validate_and_build(const lbm3_domain &d, int dom, double beta0, DomHost &H,
         H.flags[p] |= FL_FILL;
         H.fill.push_back(fn);
         H.cand.resize(H.cand.size() + 4 * kFillCands);
-        fill_candidates(D, H.flags.data(), fn, H.cand.data() + H.cand.size() - 4 * kFillCands);
+        fill_candidates(D, H.flags.data(), fn, H.cand.data() + H.cand.size() - 4 * kFillCands, &ranges);
       }
   // Interpolated bounce-back link fractions.
   for (int j = 0; j < ny; ++j)
@@ -563,6 +652,7 @@ struct lbm3_ctx {
 
   template <typename P>
   P *at(size_t off) const { return reinterpret_cast<P *>(ws + off); }
+  CandRangeCache cand_ranges;  // lbm3_set_params: fill candidates' angle ranges, by surroundings and angles
 };
 
 namespace {
@@ -1301,8 +1391,11 @@ lbm3_status lbm3_set_params(lbm3_ctx *c, int32_t domain, const double *theta_deg
                          hipMemcpyHostToDevice, c->stream));
   // the fill's candidate crossings follow the angles
   std::vector<FillCand> cand(4 * kFillCands * (size_t)std::max(D.n_fill, 1));
+  // (kept across calls: a set of angles seen before finds its ranges; bounded at ~30 MB)
+  if (c->cand_ranges.map.size() > 65536) c->cand_ranges.map.clear();
   for (int p = 0; p < D.n_fill; ++p)
-    fill_candidates(D, c->hflags.data() + D.base, c->hfill[D.fill_off + p], cand.data() + 4 * kFillCands * (size_t)p);
+    fill_candidates(D, c->hflags.data() + D.base, c->hfill[D.fill_off + p], cand.data() + 4 * kFillCands * (size_t)p,
+                    &c->cand_ranges);
   if (D.n_fill > 0)
     HIPC(c, hipMemcpyAsync(c->at<FillCand>(c->L.off_cand) + 4 * kFillCands * (size_t)D.fill_off, cand.data(),
                            sizeof(FillCand) * 4 * kFillCands * D.n_fill, hipMemcpyHostToDevice, c->stream));

@@ -15,6 +15,7 @@
 
 #include <stdint.h>
 
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -333,18 +334,64 @@ __host__ __device__ inline void sincos_quadrant(double phi, double &sn, double &
   cs = comp ? s : c;
 }
 
-// Host: the march of the fill's line at angle phi on side s (direction cos(phi) n + s sin(phi) t,
-// t = (-n_y, n_x)), and the range lo..hi of angles around phi over which the march meets its hit
-// at the same crossing, reached with counters hk (lo > hi: none; also when the line has no hit).
-// The march's crossings, their order and their node / segment classification change only near the
-// angles of rays through lattice nodes (up to the hit's distance, plus a margin) and of rays
-// parallel to an axis; between two such angles, farther from both than the node tolerance's
-// angular width (below 1e-9 for nodes at distance 1 or more), they are fixed.  When phi itself is
-// at such an angle (a ray through a node), the range is the +-2e-11 over which every crossing keeps
-// its class.  The range is kept only if the march at its ends and midpoints agrees.
+// Host: the radius of lattice nodes whose rays can change a line's march up to its hit h.
+inline int line_reach(int pi, int pj, const LineHit &h) {
+  return (int)std::ceil(std::hypot(0.5 * (h.i0 + h.i1) - pi, 0.5 * (h.j0 + h.j1) - pj) + 2.0);
+}
+
+// Host: the angles in [0, pi/2] at which the fill's line on side s (direction cos(phi) n +
+// s sin(phi) t, t = (-n_y, n_x)) is parallel to an axis or passes through a lattice node within
+// distance R of its node, sorted.  The march's crossings, their order and their node / segment
+// classification change only near these angles (for a hit within distance R - 2).
+inline std::vector<double> line_breakpoints(double nx, double ny, double s, int R) {
+  const double half_pi = 1.5707963267948966, pi2 = 6.283185307179586, tx = -ny, ty = nx;
+  // The ray to node offset q is at angle s (alpha_q - alpha_n) from the normal; the offsets' own
+  // angles alpha_q (within radius 8) are formed once.
+  constexpr int kTableR = 8;
+  struct Offset { double alpha; int r2; };
+  static const std::vector<Offset> table = [] {
+    std::vector<Offset> t;
+    for (int v = -kTableR; v <= kTableR; ++v)
+      for (int u = -kTableR; u <= kTableR; ++u)
+        if ((u || v) && u * u + v * v <= kTableR * kTableR) t.push_back({std::atan2((double)v, (double)u), u * u + v * v});
+    return t;
+  }();
+  std::vector<double> brk;
+  if (R <= kTableR) {
+    const double an = std::atan2(ny, nx);
+    for (const Offset &o : table) {
+      if (o.r2 > R * R) continue;
+      double a = s * (o.alpha - an);
+      if (a > 3.141592653589793) a -= pi2;
+      if (a <= -3.141592653589793) a += pi2;
+      if (a >= -1e-6 && a <= half_pi + 1e-6) brk.push_back(a);
+    }
+  } else {
+    for (int v = -R; v <= R; ++v)
+      for (int u = -R; u <= R; ++u) {
+        if ((u == 0 && v == 0) || u * u + v * v > R * R) continue;
+        const double a = std::atan2(s * (u * tx + v * ty), u * nx + v * ny);
+        if (a >= -1e-6 && a <= half_pi + 1e-6) brk.push_back(a);
+      }
+  }
+  for (const double a : {std::atan2(-nx, s * tx), std::atan2(-ny, s * ty), std::atan2(nx, -s * tx), std::atan2(ny, -s * ty)})
+    if (a >= -1e-6 && a <= half_pi + 1e-6) brk.push_back(a);
+  std::sort(brk.begin(), brk.end());
+  return brk;
+}
+
+// Host: the fill line's march at angle phi on side s, and the range lo..hi of angles around phi
+// over which the march meets its hit at the same crossing, reached with counters hk (lo > hi: none;
+// also when the line has no hit).  Between two breakpoints (line_breakpoints, for a radius of at
+// least the hit's distance + 2), farther from both than the node tolerance's angular width
+// (below 1e-9 for nodes at distance 1 or more), the crossings up to the hit are fixed; when phi
+// itself is at a breakpoint (a ray through a node), the range is the +-2e-11 over which every
+// crossing keeps its class.  The range is kept only if the march at both its ends agrees.
+// brk: sorted breakpoints of this side for a radius R_brk (formed here when null or too small).
 template <class FluidAt>
 inline LineHit line_angle_range(int pi, int pj, double nx, double ny, double s, double phi, const FluidAt &fluid,
-                                double &lo, double &hi, int hk[2]) {
+                                double &lo, double &hi, int hk[2], const std::vector<double> *brk = nullptr,
+                                int R_brk = 0) {
   const double half_pi = 1.5707963267948966, tx = -ny, ty = nx;
   auto march_at = [&](double a, int *k) {
     double sp, cp;
@@ -357,33 +404,26 @@ inline LineHit line_angle_range(int pi, int pj, double nx, double ny, double s, 
   hi = 0.0;
   const LineHit h = march_at(phi, hk);
   if (!h.ok) return h;
-  const double reach = std::hypot(0.5 * (h.i0 + h.i1) - pi, 0.5 * (h.j0 + h.j1) - pj) + 2.0;
-  const int R = (int)std::ceil(reach);
-  std::vector<double> brk;
-  for (int v = -R; v <= R; ++v)
-    for (int u = -R; u <= R; ++u) {
-      if ((u == 0 && v == 0) || u * u + v * v > R * R) continue;
-      const double a = std::atan2(s * (u * tx + v * ty), u * nx + v * ny);
-      if (a >= -1e-6 && a <= half_pi + 1e-6) brk.push_back(a);
-    }
-  for (const double a : {std::atan2(-nx, s * tx), std::atan2(-ny, s * ty), std::atan2(nx, -s * tx), std::atan2(ny, -s * ty)})
-    if (a >= -1e-6 && a <= half_pi + 1e-6) brk.push_back(a);
-  const double m = 1e-9;
-  double l = -1.0, u = 10.0;
-  bool on_break = false;
-  for (const double a : brk) {
-    if (std::fabs(a - phi) <= m) on_break = true;
-    else if (a < phi) l = std::fmax(l, a + m);
-    else u = std::fmin(u, a - m);
+  const int R = line_reach(pi, pj, h);
+  std::vector<double> own;
+  if (!brk || R_brk < R) {
+    own = line_breakpoints(nx, ny, s, R);
+    brk = &own;
   }
-  if (on_break) {
+  const double m = 1e-9;
+  // the nearest breakpoints below phi - m and above phi + m, and whether one lies within m
+  const auto b_lo = std::lower_bound(brk->begin(), brk->end(), phi - m);
+  const auto b_hi = std::upper_bound(brk->begin(), brk->end(), phi + m);
+  double l = b_lo == brk->begin() ? -1.0 : *(b_lo - 1) + m;
+  double u = b_hi == brk->end() ? 10.0 : *b_hi - m;
+  if (b_lo != b_hi) {  // a ray through a node
     l = phi - 2e-11;
     u = phi + 2e-11;
   }
   l = std::fmax(l, 0.0);
   u = std::fmin(u, half_pi);
   if (!(l <= phi && phi <= u)) return h;
-  for (const double a : {l, 0.5 * (l + phi), 0.5 * (phi + u), u}) {
+  for (const double a : {l, u}) {
     int k2[2];
     const LineHit g = march_at(a, k2);
     if (!(g.ok && g.i0 == h.i0 && g.j0 == h.j0 && g.i1 == h.i1 && g.j1 == h.j1 && k2[0] == hk[0] && k2[1] == hk[1]))

@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <random>
+#include <vector>
 
 #include "lbm3_internal.h"
 
@@ -85,21 +86,35 @@ int main(int argc, char **argv) {
       double lo, hi;
       int hk[2];
       const LineHit c = line_angle_range(pi, pj, nx, ny, s, phi, fluid, lo, hi, hk);
-      if (lo <= hi) {
-        ++ranges;
-        for (int q = 0; q < 8; ++q) {
-          const double f = q == 0 ? lo : (q == 1 ? hi : (q == 2 ? phi : lo + (hi - lo) * U(g)));
-          double sp, cp;
-          sincos_quadrant(f, sp, cp);
-          sp *= s;
-          const double ex = cp * nx + sp * -ny, ey = cp * ny + sp * nx;
-          const LineHit full = march_line(pi, pj, ex, ey, fluid);
-          const LineHit from = march_line_masked(pi, pj, ex, ey, mask, far, fluid, hk[0], hk[1]);
-          const bool same = full.ok == from.ok && full.ok && full.i0 == from.i0 && full.j0 == from.j0 &&
-                            full.i1 == from.i1 && full.j1 == from.j1 && full.w == from.w && full.i0 == c.i0 &&
-                            full.j0 == c.j0 && full.i1 == c.i1 && full.j1 == c.j1;
-          if (!same && ++bad_range <= 5)
-            std::printf("range mismatch, trial %ld phi %.17g in [%.17g, %.17g] at %.17g\n", trial, phi, lo, hi, f);
+      // breakpoints shared at a larger radius (as the set-up forms them, one set per side): the
+      // same hit and counters, and a range checked below as this one is
+      double lo2, hi2;
+      int hk2[2];
+      const int Rb = c.ok ? line_reach(pi, pj, c) + (int)(U(g) * 6) : 3;
+      const std::vector<double> brk = line_breakpoints(nx, ny, s, Rb);
+      const LineHit c2 = line_angle_range(pi, pj, nx, ny, s, phi, fluid, lo2, hi2, hk2, &brk, Rb);
+      if (!(c2.ok == c.ok && (!c.ok || (c2.i0 == c.i0 && c2.j0 == c.j0 && c2.i1 == c.i1 && c2.j1 == c.j1 &&
+                                        hk2[0] == hk[0] && hk2[1] == hk[1]))) && ++bad_range <= 5)
+        std::printf("shared breakpoints: another hit, trial %ld phi %.17g\n", trial, phi);
+      for (int pass = 0; pass < 2; ++pass) {
+        const double lo_ = pass ? lo2 : lo, hi_ = pass ? hi2 : hi;
+        const int kx_ = pass ? hk2[0] : hk[0], ky_ = pass ? hk2[1] : hk[1];
+        if (lo_ <= hi_) {
+          ++ranges;
+          for (int q = 0; q < 8; ++q) {
+            const double f = q == 0 ? lo_ : (q == 1 ? hi_ : (q == 2 ? phi : lo_ + (hi_ - lo_) * U(g)));
+            double sp, cp;
+            sincos_quadrant(f, sp, cp);
+            sp *= s;
+            const double ex = cp * nx + sp * -ny, ey = cp * ny + sp * nx;
+            const LineHit full = march_line(pi, pj, ex, ey, fluid);
+            const LineHit from = march_line_masked(pi, pj, ex, ey, mask, far, fluid, kx_, ky_);
+            const bool same = full.ok == from.ok && full.ok && full.i0 == from.i0 && full.j0 == from.j0 &&
+                              full.i1 == from.i1 && full.j1 == from.j1 && full.w == from.w && full.i0 == c.i0 &&
+                              full.j0 == c.j0 && full.i1 == c.i1 && full.j1 == c.j1;
+            if (!same && ++bad_range <= 5)
+              std::printf("range mismatch, trial %ld phi %.17g in [%.17g, %.17g] at %.17g\n", trial, phi, lo_, hi_, f);
+          }
         }
       }
     }
