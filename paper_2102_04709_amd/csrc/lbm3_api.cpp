@@ -15,10 +15,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <unordered_map>
 #include <vector>
 
@@ -164,7 +166,7 @@ void param_jacobian(const double *theta_deg, const double *sigma, double J[9][5]
 // the candidate angles and the fluid flags its marches test: when every candidate's march stays in
 // the node's 11 x 11 block, on the node's fluid mask (FillNode::mask), so nodes with the same
 // mask and normal (flat walls) share them.
-constexpr int kRangeReach = 8;
+constexpr int kRangeReach = 26;
 struct CandRangeCache {
   struct Entry {
     int32_t rel[4 * kFillCands][4];  // the crossing's nodes relative to the fill node
@@ -533,8 +535,22 @@ bool plan(const lbm3_domain *d, int n, const lbm3_options *o, std::vector<DomHos
       return err = m, false;
     }
   H.assign(n, DomHost());
-  for (int i = 0; i < n; ++i)
-    if (!validate_and_build(d[i], i, beta0, H[i], err)) return false;
+  {  // the domains are independent: up to 16 host threads take them in turn; the first failing
+     // domain (in index order) reports
+    std::vector<std::string> errs(n);
+    std::vector<char> ok(n, 0);
+    std::atomic<int> next{0};
+    auto work = [&]() {
+      for (int i; (i = next.fetch_add(1)) < n;) ok[i] = validate_and_build(d[i], i, beta0, H[i], errs[i]);
+    };
+    const int nt = std::min(n, std::max(1, std::min(16, (int)std::thread::hardware_concurrency())));
+    std::vector<std::thread> pool;
+    for (int t = 1; t < nt; ++t) pool.emplace_back(work);
+    work();
+    for (std::thread &t : pool) t.join();
+    for (int i = 0; i < n; ++i)
+      if (!ok[i]) return err = errs[i], false;
+  }
   if (o->adjoint != 0 && o->adjoint != 1) return err = "adjoint must be 0 or 1", false;
   if (o->adjoint && o->precision == LBM3_F32_STORE_F16) return err = "the adjoint needs LBM3_F64 or LBM3_F32", false;
   int64_t base = 0, abase = 0, goff = 0;

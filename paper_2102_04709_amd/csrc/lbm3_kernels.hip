@@ -89,7 +89,7 @@ struct Smem {
   T *PR;                 // ring 1, 4 planes: R_1, R_2 of the recolouring
   uint8_t *FL;           // ring 3: flags
   int *any_stress;       // set in phase B when some pair normal of the tile + 2 rings is nonzero
-  int *present;          // phase A: bit k set when some C_k of the tile + 3 rings is nonzero
+  int *present_w;        // phase A, one per wave: bit k set when some C_k the wave formed is nonzero
 };
 
 template <typename T>
@@ -97,7 +97,7 @@ __host__ __device__ inline size_t smem_bytes(int TX, int TY) {
   const size_t n3 = (size_t)(TX + 6) * (TY + 6), n2 = (size_t)(TX + 4) * (TY + 4),
                n1 = (size_t)(TX + 2) * (TY + 2);
   const size_t shared = 3 * n2 > 9 * n1 ? 3 * n2 : 9 * n1;
-  return (3 * n3 + n2 + shared + 4 * n1) * sizeof(T) + ((n3 + 15) & ~(size_t)15) + 16;
+  return (3 * n3 + n2 + shared + 4 * n1) * sizeof(T) + ((n3 + 15) & ~(size_t)15) + 48;
 }
 
 template <typename T, int W1, int W3, int N1>
@@ -140,7 +140,7 @@ void step_fused(StepArgs<S, T> A) {
     L.PR = p; p += 4 * N1;
     L.FL = reinterpret_cast<uint8_t *>(p);
     L.any_stress = reinterpret_cast<int *>(L.FL + ((N3 + 15) & ~15));
-    L.present = L.any_stress + 1;
+    L.present_w = L.any_stress + 4;
   }
   constexpr bool FIELDS = OUT == OUT_FIELDS, ADJ = OUT == OUT_ADJ;
   // single-fluid tiles skip phase B in the streaming step; not in the 16-wide tiles, where the
@@ -149,8 +149,6 @@ void step_fused(StepArgs<S, T> A) {
   constexpr bool SKIP1 = !FIELDS && !ADJ && TX >= 32;
   const int tid = threadIdx.x;
   const T eps_g = A.eps_g;
-  if (tid == 0) *L.present = 0;  // (phase C clears it again after each work item's phase B reads it)
-  __syncthreads();
 
   for (int wi = A.work_begin + first_item(A.remap); wi < A.work_end; wi += A.remap ? A.work_end : gridDim.x) {
     const WorkItem wk = A.work[wi];
@@ -186,9 +184,10 @@ void step_fused(StepArgs<S, T> A) {
         }
       }
     }
-    if (SKIP1) {  // the fluids present in the tile + 3 rings: one LDS OR per wave
+    if (SKIP1) {  // the fluids present in the wave's positions: one LDS word per wave (each wave
+                  // writes its own every work item, so nothing needs clearing)
       const int wf = (__ballot(fluids & 1) ? 1 : 0) | (__ballot(fluids & 2) ? 2 : 0) | (__ballot(fluids & 4) ? 4 : 0);
-      if ((tid & 63) == 0 && wf) atomicOr(L.present, wf);
+      if ((tid & 63) == 0) L.present_w[tid >> 6] = wf;
     }
     __syncthreads();
 
@@ -197,7 +196,12 @@ void step_fused(StepArgs<S, T> A) {
     // G_kl = C_l grad C_k - C_k grad C_l = 0 for every pair, so no pair passes |G| > eps: phase B
     // would leave the stress +0 and the normals zero, which the force loop and the plain streaming
     // of such a tile do not read (they are skipped below), so it is skipped as well.
-    const int fluids_here = __builtin_amdgcn_readfirstlane(*L.present);  // (uniform: a scalar)
+    int fluids_here = 0;  // the fluids present in the tile + 3 rings (uniform: a scalar)
+    if (SKIP1) {
+#pragma unroll
+      for (int w = 0; w < NT / 64; ++w) fluids_here |= L.present_w[w];
+      fluids_here = __builtin_amdgcn_readfirstlane(fluids_here);
+    }
     const bool single_fluid = SKIP1 && plain && (fluids_here & (fluids_here - 1)) == 0;
     bool any_g = false;
     for (int q = single_fluid ? N2 : tid; q < N2; q += NT) {
@@ -243,7 +247,6 @@ void step_fused(StepArgs<S, T> A) {
     }
     if (any_g) *L.any_stress = 1;
     __syncthreads();
-    if (tid == 0) *L.present = 0;  // every thread read it before the barrier above
 
     // Phase C: force (all ring-1 nodes first: the populations then overwrite the stress),
     // velocity and MRT collision on tile + 1 ring.
