@@ -11,8 +11,10 @@ SOURCES = [os.path.join(CSRC, f) for f in ("lbm3_kernels.hip", "lbm3_adjoint.hip
 HEADERS = [os.path.join(CSRC, f) for f in ("lbm3_internal.h", "lbm3_kernels.h", "lbm3_device.h", "lbm3_adjoint.h")] + [
     os.path.join(ROOT, "include", "lbm3.h")]
 
+# (kernel-argument preloading: the first 8 dwords of a kernel's scalar arguments arrive in SGPRs,
+# with the compiler's fallback prologue for firmware that does not preload)
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=on",
-         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-mllvm", "-amdgpu-kernarg-preload-count=8",
          "-I" + os.path.join(ROOT, "include"), "-I" + CSRC, "-Wall", "-Wno-unused-function"]
 
 

@@ -1548,27 +1548,35 @@ lbm3_status lbm3_autotune(lbm3_ctx *c, int32_t steps_per_candidate, int32_t *cho
             cached = true;
           }
   }
-  for (const Candidate &t : kCands) {
-    if (cached) break;
-    if (is_tile_mode(t.kernel) && step_smem_bytes(c->precision, t.kernel, t.tx, t.ty) > 160 * 1024) continue;
-    if (!is_tile_mode(t.kernel) && step_smem_bytes(c->precision, t.kernel, 0, 0) > 160 * 1024) continue;
-    c->mode = t.kernel;
-    c->tx = t.tx;
-    c->ty = t.ty;
-    build_work(c);
-    lbm3_status st = upload_tables(c);
-    if (st != LBM3_OK) return st;
-    st = enqueue_steps(c, 2, c->stream);  // warm-up
-    if (st != LBM3_OK) return st;
-    c->steps += 2;
-    double mf, ms;
-    st = lbm3_kernel_times(c, steps_per_candidate, &mf, &ms);
-    if (st != LBM3_OK) return st;
-    if (mf + ms < best) {  // the whole step: a separate fill kernel counts too
-      best = mf + ms;
-      bc = t;
+  // Two rounds over the candidates, each candidate's best round counting: close configurations
+  // (at small sizes within a few per cent) are then not picked by one noisy timing.
+  constexpr int kRounds = 2;
+  double cand_best[sizeof(kCands) / sizeof(kCands[0])];
+  for (double &b : cand_best) b = 1e300;
+  for (int round = 0; round < kRounds && !cached; ++round)
+    for (size_t ci = 0; ci < sizeof(kCands) / sizeof(kCands[0]); ++ci) {
+      const Candidate &t = kCands[ci];
+      if (is_tile_mode(t.kernel) && step_smem_bytes(c->precision, t.kernel, t.tx, t.ty) > 160 * 1024) continue;
+      if (!is_tile_mode(t.kernel) && step_smem_bytes(c->precision, t.kernel, 0, 0) > 160 * 1024) continue;
+      c->mode = t.kernel;
+      c->tx = t.tx;
+      c->ty = t.ty;
+      build_work(c);
+      lbm3_status st = upload_tables(c);
+      if (st != LBM3_OK) return st;
+      st = enqueue_steps(c, 2, c->stream);  // warm-up
+      if (st != LBM3_OK) return st;
+      c->steps += 2;
+      double mf, ms;
+      st = lbm3_kernel_times(c, steps_per_candidate, &mf, &ms);
+      if (st != LBM3_OK) return st;
+      cand_best[ci] = std::min(cand_best[ci], mf + ms);  // the whole step: a separate fill kernel counts too
     }
-  }
+  for (size_t ci = 0; ci < sizeof(kCands) / sizeof(kCands[0]) && !cached; ++ci)
+    if (cand_best[ci] < best) {
+      best = cand_best[ci];
+      bc = kCands[ci];
+    }
   c->mode = bc.kernel;
   c->tx = bc.tx;
   c->ty = bc.ty;

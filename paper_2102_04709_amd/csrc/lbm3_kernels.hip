@@ -32,15 +32,20 @@ namespace lbm3 {
 // (so the domain's constants load with the node records instead of after them).  The three
 // filled C's go to the compact array fillC[3 * node] that the fused kernels read (so the solid
 // slots of the state stay constant).
+// blocks .. doms: the fields of A that the first two rounds of loads need, as scalar arguments,
+// which the compiler preloads into registers at wave launch (A's copies are not read).
 template <typename T>
-__global__ __launch_bounds__(4 * kFillNodes) void wet_fill(FillArgs<T> A) {
+__global__ __launch_bounds__(4 * kFillNodes) void wet_fill(const FillBlock *__restrict__ blocks,
+                                                           const FillNode *__restrict__ fill,
+                                                           const FillCand *__restrict__ cand,
+                                                           const DomainDev *__restrict__ doms, FillArgs<T> A) {
   __shared__ uint32_t far[kFillNodes][kFarW];  // the nodes' far fluid masks (for lines leaving the near one)
-  const FillBlock B = A.blocks[blockIdx.x];
-  const DomainDev &D = A.doms[B.dom];
+  const FillBlock B = blocks[blockIdx.x];
+  const DomainDev &D = doms[B.dom];
   const int e = threadIdx.x >> 2, line = threadIdx.x & 3;
   const bool active = e < B.count;
   const int idx = B.first + (active ? e : 0);
-  const FillNode fn = A.fill[idx];
+  const FillNode fn = fill[idx];
   // The far mask is loaded with the node and stored to LDS once the densities at D0 are in.
   constexpr int kFarPerLane = (kFarW + 3) / 4;
   uint32_t fr[kFarPerLane];
@@ -57,7 +62,7 @@ __global__ __launch_bounds__(4 * kFillNodes) void wet_fill(FillArgs<T> A) {
   };
   double c1, c2;
   fill_lanes<T>(fn, D, A.flags + D.base, A.rho + 3 * D.base, far[e], stage, line, active, c1, c2,
-                A.cand + ((size_t)idx * 4 + line) * kFillCands);
+                cand + ((size_t)idx * 4 + line) * kFillCands);
   if (active && line == 0) {
     A.fillC[3 * idx] = (T)c1;
     A.fillC[3 * idx + 1] = (T)c2;
@@ -72,6 +77,13 @@ __device__ __forceinline__ int first_item(int remap) {
   if (!remap) return blockIdx.x;
   const int per = gridDim.x >> 3;
   return (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+}
+
+// The same with the groups per XCD (grid / 8) given by the launch, which the tile kernel takes as
+// a scalar argument: preloaded into registers with the other leading arguments, so the first work
+// item's address needs no load.
+__device__ __forceinline__ int first_item(int remap, int per) {
+  return remap ? (blockIdx.x & 7) * per + (blockIdx.x >> 3) : blockIdx.x;
 }
 
 // ------------------------------------------------------------------------------------------
@@ -126,7 +138,10 @@ struct TileAcc {
 // (0.552 -> 0.418 ms per 4000 x 4000 launch at 6 waves); the FP64 ones are limited by their LDS.
 template <typename S, typename T, int OUT, int TX, int TY, int NT>
 __global__ __launch_bounds__(NT, sizeof(T) == 8 ? 1 : (sizeof(S) == 2 ? ((TX == 64 && NT == 512) ? 6 : 5) : 6))
-void step_fused(StepArgs<S, T> A) {
+void step_fused(const WorkItem *__restrict__ work, const DomainDev *__restrict__ doms, int work_begin, int work_end,
+                int remap, int per, StepArgs<S, T> A) {
+  // (work .. per: the leading fields of A that locate the first work item, as scalar arguments,
+  // which the compiler preloads into registers at wave launch; A's copies are not read)
   extern __shared__ __align__(16) unsigned char smem_raw[];
   constexpr int W3 = TX + 6, H3 = TY + 6, N3 = W3 * H3;
   constexpr int W2 = TX + 4, H2 = TY + 4, N2 = W2 * H2;
@@ -150,9 +165,9 @@ void step_fused(StepArgs<S, T> A) {
   const int tid = threadIdx.x;
   const T eps_g = A.eps_g;
 
-  for (int wi = A.work_begin + first_item(A.remap); wi < A.work_end; wi += A.remap ? A.work_end : gridDim.x) {
-    const WorkItem wk = A.work[wi];
-    const DomainDev &D = A.doms[wk.dom];
+  for (int wi = work_begin + first_item(remap, per); wi < work_end; wi += remap ? work_end : gridDim.x) {
+    const WorkItem wk = work[wi];
+    const DomainDev &D = doms[wk.dom];
     const int x0 = wk.x0, y0 = wk.y0;
     const uint8_t *flags = A.flags + D.base;
     const T *Rin = A.rin + 3 * D.base;
@@ -626,7 +641,7 @@ __global__ void mass_final(const double *partial, const int *chunk_first, int n_
 template <typename T>
 hipError_t launch_fill(const FillArgs<T> &a, hipStream_t s) {
   if (a.n_fill <= 0 || a.n_blocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(wet_fill<T>, dim3(a.n_blocks), dim3(4 * kFillNodes), 0, s, a);
+  hipLaunchKernelGGL(wet_fill<T>, dim3(a.n_blocks), dim3(4 * kFillNodes), 0, s, a.blocks, a.fill, a.cand, a.doms, a);
   return hipGetLastError();
 }
 
@@ -648,7 +663,8 @@ template <typename S, typename T>
 hipError_t launch_step(const StepArgs<S, T> &a, int grid, int mode, int out, hipStream_t s) {
   if (out == OUT_ADJ) {  // the adjoint's tiles: 32 x 8, 256 threads
     if (a.tile_x != 32 || a.tile_y != 8) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((step_fused<S, T, OUT_ADJ, 32, 8, 256>), dim3(grid), dim3(256), smem_bytes<T>(32, 8), s, a);
+    hipLaunchKernelGGL((step_fused<S, T, OUT_ADJ, 32, 8, 256>), dim3(grid), dim3(256), smem_bytes<T>(32, 8), s, a.work,
+                       a.doms, a.work_begin, a.work_end, a.remap, grid >> 3, a);
     return hipGetLastError();
   }
   const bool fields = out == OUT_FIELDS;
@@ -657,8 +673,10 @@ hipError_t launch_step(const StepArgs<S, T> &a, int grid, int mode, int out, hip
     const int nt = (!fields && mode == MODE_TILE512) ? 512 : 256;
 #define LBM3_TL(X, Y, N)                                                                           \
     if (a.tile_x == X && a.tile_y == Y && nt == N) {                                               \
-      if (fields) hipLaunchKernelGGL((step_fused<S, T, OUT_FIELDS, X, Y, N>), dim3(grid), dim3(N), sm, s, a); \
-      else hipLaunchKernelGGL((step_fused<S, T, OUT_STEP, X, Y, N>), dim3(grid), dim3(N), sm, s, a);         \
+      if (fields) hipLaunchKernelGGL((step_fused<S, T, OUT_FIELDS, X, Y, N>), dim3(grid), dim3(N), sm, s, a.work, a.doms,     \
+                                     a.work_begin, a.work_end, a.remap, grid >> 3, a);                              \
+      else hipLaunchKernelGGL((step_fused<S, T, OUT_STEP, X, Y, N>), dim3(grid), dim3(N), sm, s, a.work, a.doms, a.work_begin, \
+                              a.work_end, a.remap, grid >> 3, a);                                                   \
       return hipGetLastError();                                                                    \
     }
     LBM3_TILE_SHAPES(LBM3_TL)
