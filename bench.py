@@ -29,10 +29,10 @@ HBM_PEAK_GBS = 8000.0
 # precision and kernel configuration, valid for the kernel sources with the given digest only.
 KERNEL_SOURCES = ("lbm3_kernels.hip", "lbm3_device.h", "lbm3_internal.h", "lbm3_kernels.h", "lbm3_adjoint.h")
 TRAFFIC = {
-    "digest": "ed29f6e34167d722",
-    ('cylinder_janus', 400, 'f32', (3, 16, 16)): (4464.0 * 2.0 + 6969.0 * 1.0) * 1024,
-    ('cylinder_janus_x10', 4000, 'f32', (3, 64, 8)): (362868.2 * 2.0 + 696999.0 * 1.0) * 1024,
-    ('cylinder_janus_x10', 4000, 'f16', (3, 64, 8)): (232856.5 * 2.0 + 435784.1 * 1.0) * 1024,
+    "digest": "09d76c66367a9433",
+    ('cylinder_janus', 400, 'f32', (3, 16, 16)): (4478.0 * 2.0 + 6969.0 * 1.0) * 1024,
+    ('cylinder_janus_x10', 4000, 'f32', (3, 64, 8)): (363611.0 * 2.0 + 696999.0 * 1.0) * 1024,
+    ('cylinder_janus_x10', 4000, 'f16', (3, 64, 8)): (233596.3 * 2.0 + 435784.1 * 1.0) * 1024,
 }
 
 

@@ -776,6 +776,13 @@ void build_adjoint_work(lbm3_ctx *c) {
 }
 
 lbm3_status upload_tables(lbm3_ctx *c) {
+  for (std::vector<WorkItem> *v : {&c->work, &c->fwork, &c->awork})
+    for (WorkItem &w : *v) {
+      const DomainDev &D = c->doms[w.dom];
+      w.pitch = D.pitch;
+      w.base = D.base;
+      w.plane = D.plane;
+    }
   if (!c->tibb.empty())
     HIPC(c, hipMemcpyAsync(c->at<void>(c->L.off_tibb), c->tibb.data(), sizeof(TileIbb) * c->tibb.size(),
                            hipMemcpyHostToDevice, c->stream));

@@ -127,8 +127,12 @@ struct IbbNode {
 // exchanging x boundary column (streaming is a plain pull).
 enum : int32_t { WK_INNER = 1, WK_PLAIN = 2 };
 // ibb_begin, ibb_count: the item's range of TileIbb entries (tiles of the step; zero otherwise).
+// pitch, base, plane: the domain's row pitch, state offset and plane size (as in DomainDev),
+// repeated here so that a tile's first loads need its work item only.
 struct WorkItem {
   int32_t dom, x0, y0, x1, y1, kind, ibb_begin, ibb_count;
+  int32_t pitch = 0, pad_ = 0;
+  int64_t base = 0, plane = 0;
 };
 
 // An interpolated-bounce-back node of a step tile: its position q = lx + TX ly in the tile and the

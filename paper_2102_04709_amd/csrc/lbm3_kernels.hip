@@ -169,10 +169,13 @@ void step_fused(const WorkItem *__restrict__ work, const DomainDev *__restrict__
     const WorkItem wk = work[wi];
     const DomainDev &D = doms[wk.dom];
     const int x0 = wk.x0, y0 = wk.y0;
-    const uint8_t *flags = A.flags + D.base;
-    const T *Rin = A.rin + 3 * D.base;
-    const S *Fin = A.fin + 9 * D.base;
-    const int64_t P = D.plane;
+    // (the state's offset, plane and pitch from the work item: the first loads need not wait for
+    // the domain record)
+    const int pitch = wk.pitch;
+    const uint8_t *flags = A.flags + wk.base;
+    const T *Rin = A.rin + 3 * wk.base;
+    const S *Fin = A.fin + 9 * wk.base;
+    const int64_t P = wk.plane;
     const KT<T> K = make_kt<T>(D);
     const bool inner = wk.kind & WK_INNER, plain = wk.kind & WK_PLAIN;
 
@@ -181,7 +184,7 @@ void step_fused(const WorkItem *__restrict__ work, const DomainDev *__restrict__
     int fluids = 0;  // bit k: some C_k this thread formed is nonzero
     for (int q = tid; q < N3; q += NT) {
       const int lx = q % W3, ly = q / W3;
-      const int64_t li = inner ? plane_index(x0 - 3 + lx, y0 - 3 + ly, D.pitch)
+      const int64_t li = inner ? plane_index(x0 - 3 + lx, y0 - 3 + ly, pitch)
                                : node_index(x0 - 3 + lx, y0 - 3 + ly, D);
       const uint8_t fl = *elem32(flags, li);
       T v[4];
@@ -320,7 +323,7 @@ void step_fused(const WorkItem *__restrict__ work, const DomainDev *__restrict__
       }
       T f[9];
       {
-        const int64_t li = inner ? plane_index(gx, gy, D.pitch) : node_index(gx, gy, D);
+        const int64_t li = inner ? plane_index(gx, gy, pitch) : node_index(gx, gy, D);
 #pragma unroll
         for (int a = 0; a < 9; ++a) f[a] = load_s<S, T>(elem32(Fin + a * P, li));
       }
@@ -355,7 +358,7 @@ void step_fused(const WorkItem *__restrict__ work, const DomainDev *__restrict__
         const int lx = q % TX, ly = q / TX;
         const int gx = x0 + lx, gy = y0 + ly;
         if (gx >= D.nx || gy >= D.ny) continue;
-        const int64_t li = plane_index(gx, gy, D.pitch);
+        const int64_t li = plane_index(gx, gy, pitch);
         const int64_t o = (int64_t)gy * D.nx + gx, n = (int64_t)D.nx * D.ny;
         const bool solid = flags[li] & FL_SOLID;
         const int p3 = (lx + 3) + (ly + 3) * W3;
@@ -386,13 +389,13 @@ void step_fused(const WorkItem *__restrict__ work, const DomainDev *__restrict__
     }
 
     // Phase D: pull-streaming into the tile, Eq. (16), with the boundary rules.
-    T *Rout = A.rout + 3 * D.base;
-    S *Fout = A.fout + 9 * D.base;
+    T *Rout = A.rout + 3 * wk.base;
+    S *Fout = A.fout + 9 * wk.base;
     for (int q = tid; q < TX * TY; q += NT) {
       const int lx = q % TX, ly = q / TX;
       const int gx = x0 + lx, gy = y0 + ly;
       if (gx >= D.nx || gy >= D.ny) continue;
-      const int64_t li = plane_index(gx, gy, D.pitch);
+      const int64_t li = plane_index(gx, gy, pitch);
       const int p1 = (lx + 1) + (ly + 1) * W1;
       const int p3 = (lx + 3) + (ly + 3) * W3;
       const uint8_t fl = L.FL[p3];
