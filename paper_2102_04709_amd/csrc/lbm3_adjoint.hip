@@ -80,8 +80,10 @@ __device__ __forceinline__ void block_add(const double (&v)[N], double *dst) {
 // Work item of this work-group: consecutive items go to the same XCD (gfx950 dispatches
 // work-group b to XCD b mod 8), so the tiles an XCD processes are contiguous and share their halo
 // rows in that XCD's L2.  The grid is a multiple of 8; the padding groups have no item (-1).
-__device__ __forceinline__ int adj_item(int n_work) {
-  const int per = gridDim.x >> 3;
+// per: the groups per XCD (grid / 8), given by the launch as a scalar argument, which the
+// compiler preloads into registers with the kernel's other leading arguments (work, doms, n_work:
+// the fields of AdjArgs that locate the first tile, whose copies in AdjArgs are not read).
+__device__ __forceinline__ int adj_item(int n_work, int per) {
   const int wi = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
   return wi < n_work ? wi : -1;
 }
@@ -448,12 +450,13 @@ __device__ __forceinline__ void collide_recolour_vjp(const T f[9], T Fxi, T Fyi,
 // Adjoint of streaming and of the per-node collision and recolouring, node by node.  At solid
 // positions of the grid it clears the adjoint of C (the stress and stencil transposes add there).
 template <typename S, typename T>
-__global__ __launch_bounds__(kThreads) void adj_node(AdjArgs<S, T> A, int64_t tplane) {
+__global__ __launch_bounds__(kThreads) void adj_node(const WorkItem *__restrict__ work, const DomainDev *__restrict__ doms, int n_work, int per, 
+                                                     AdjArgs<S, T> A, int64_t tplane) {
   __shared__ T sL[12][kAdjN1];
-  const int wi = adj_item(A.n_work);
+  const int wi = adj_item(n_work, per);
   if (wi < 0) return;
-  const WorkItem wk = A.work[wi];
-  const DomainDev &D = A.doms[wk.dom];
+  const WorkItem wk = work[wi];
+  const DomainDev &D = doms[wk.dom];
   int i, j;
   double graw[3] = {0, 0, 0};
   const int64_t AP = A.aplane;
@@ -577,14 +580,15 @@ __device__ __forceinline__ void pair_stress_vjp(const T cc[3], const T g[3][2], 
 // The adjoint of the colour gradients at z then goes through the transpose of the Eq. (12)
 // stencil: an atomic scatter to the adjoint of C at the (clamped / wrapped) nodes z + e_a.
 template <typename S, typename T>
-__global__ __launch_bounds__(kThreads) void adj_stress(AdjArgs<S, T> A) {
+__global__ __launch_bounds__(kThreads) void adj_stress(const WorkItem *__restrict__ work, const DomainDev *__restrict__ doms, int n_work, int per, 
+                                                       AdjArgs<S, T> A) {
   __shared__ T sC[3][kAdjN1];       // C_k at the nodes the ring-1 block's reads see
   __shared__ T sF[2][kAdjN1];       // adjoint force at the block's (wrapped) positions, fluid only
   __shared__ uint8_t sFl[kAdjN1];   // whether that position is a fluid node
-  const int wi = adj_item(A.n_work);
+  const int wi = adj_item(n_work, per);
   if (wi < 0) return;
-  const WorkItem wk = A.work[wi];
-  const DomainDev &D = A.doms[wk.dom];
+  const WorkItem wk = work[wi];
+  const DomainDev &D = doms[wk.dom];
   const int64_t AP = A.aplane;
   for (int p = threadIdx.x; p < kAdjN1; p += kThreads) {
     const int gi = wk.x0 - 1 + p % kAdjW1, gj = wk.y0 - 1 + p / kAdjW1;
@@ -676,11 +680,12 @@ __global__ __launch_bounds__(kThreads) void adj_stress(AdjArgs<S, T> A) {
 
 // Adjoint of C_k = rho_k / rho, rho = sum_k rho_k at fluid nodes.
 template <typename S, typename T>
-__global__ __launch_bounds__(kThreads) void adj_comp(AdjArgs<S, T> A, int64_t tplane) {
-  const int wi = adj_item(A.n_work);
+__global__ __launch_bounds__(kThreads) void adj_comp(const WorkItem *__restrict__ work, const DomainDev *__restrict__ doms, int n_work, int per, 
+                                                     AdjArgs<S, T> A, int64_t tplane) {
+  const int wi = adj_item(n_work, per);
   if (wi < 0) return;
-  const WorkItem wk = A.work[wi];
-  const DomainDev &D = A.doms[wk.dom];
+  const WorkItem wk = work[wi];
+  const DomainDev &D = doms[wk.dom];
   int i, j;
   if (!tile_node(wk, i, j) || i < 0 || i >= D.nx) return;
   const int64_t li = plane_index(i, j, D.pitch);
@@ -933,9 +938,9 @@ __global__ void loss_final(const double *part, const int *first, int n_dom, doub
 template <typename S, typename T>
 hipError_t launch_adjoint(const AdjArgs<S, T> &a, int64_t tplane, hipStream_t s) {
   const dim3 g((a.n_work + 7) / 8 * 8), b(kThreads);
-  hipLaunchKernelGGL((adj_node<S, T>), g, b, 0, s, a, tplane);
-  hipLaunchKernelGGL((adj_stress<S, T>), g, b, 0, s, a);
-  hipLaunchKernelGGL((adj_comp<S, T>), g, b, 0, s, a, tplane);
+  hipLaunchKernelGGL((adj_node<S, T>), g, b, 0, s, a.work, a.doms, a.n_work, (int)(g.x >> 3), a, tplane);
+  hipLaunchKernelGGL((adj_stress<S, T>), g, b, 0, s, a.work, a.doms, a.n_work, (int)(g.x >> 3), a);
+  hipLaunchKernelGGL((adj_comp<S, T>), g, b, 0, s, a.work, a.doms, a.n_work, (int)(g.x >> 3), a, tplane);
   if (a.n_fill > 0)
     hipLaunchKernelGGL((adj_fill<S, T>), dim3((4 * a.n_fill + kThreads - 1) / kThreads), b, 0, s, a, tplane);
   return hipGetLastError();
